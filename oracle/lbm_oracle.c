@@ -40,11 +40,15 @@
  *            history = current values so every d/dt term is 0 at the first
  *            collision; distributions = equilibria (procedure step 1).
  *   R-FB     F_b = (rho - rho_ref) g + (1 - phi0) f_b.
+ *   R-CLAMP  the density and viscosity laws (Eq. rho) are evaluated on phi
+ *            clamped to [-1, 1] (overshoots past -1 would make rho <= 0 at
+ *            density ratios >= 100); grad rho is the gradient of that field.
  *   Stationary solids only: u_s = 0 and the mu_phi0 grad phi0 force, which
  *   the paper adds only for freely moving solids, is absent.
  *   Periodic in x and y.
  */
 #include <math.h>
+#include <omp.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -410,6 +414,7 @@ static void macro(orc_state *st, int init)
     /* step 3: density and viscosity laws (Eq. rho) */
     for (long o = 0; o < N; ++o) {
         double ph = F[F_PHI][o];
+        ph = ph < -1.0 ? -1.0 : (ph > 1.0 ? 1.0 : ph); /* R-CLAMP */
         F[F_RHO][o] = (p->rho1 - p->rho2) / 2.0 * ph + (p->rho1 + p->rho2) / 2.0;
         F[F_MUV][o] = (p->mu1 - p->mu2) / 2.0 * ph + (p->mu1 + p->mu2) / 2.0;
     }
@@ -605,6 +610,7 @@ void orc_step(orc_state *st, long nsteps)
 }
 
 long orc_steps_done(const orc_state *st) { return st->steps; }
+int orc_threads(void) { return omp_get_max_threads(); }
 int orc_nfields(void) { return NFIELDS; }
 const char *orc_field_name(int k) { return (k >= 0 && k < NFIELDS) ? FIELD_NAMES[k] : NULL; }
 

@@ -85,6 +85,7 @@ def lib():
         L.orc_grad.argtypes = [ctypes.c_int, ctypes.c_int, _D, _D, _D]
         L.orc_lap.argtypes = [ctypes.c_int, ctypes.c_int, _D, _D]
         L.orc_mu.argtypes = [ctypes.POINTER(OrcParams), _D, _D, _D, _D]
+        L.orc_threads.restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -102,6 +103,11 @@ def make_params(p: dict) -> OrcParams:
     for name, _ in OrcParams._fields_:
         setattr(op, name, p[name])
     return op
+
+
+def threads() -> int:
+    """OpenMP threads the collision loop uses."""
+    return int(lib().orc_threads())
 
 
 # ---------------------------------------------------------------- unit level

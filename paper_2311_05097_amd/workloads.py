@@ -27,7 +27,7 @@ PAPER_DEFAULTS = dict(
     rho1=1.0, rho2=1.0, mu1=0.1, mu2=0.1,
     tau_phi=1.0, s0=1.0, s1=1.0, s2=1.0, s3=1.0, s4=1.0,
     gx=0.0, gy=0.0, rho_ref=0.0, fbx=0.0, fby=0.0,
-    solid_eps=1e-6,
+    solid_eps=1e-2,
 )
 
 

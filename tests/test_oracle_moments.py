@@ -139,7 +139,13 @@ def test_viscous_rates(orc):
             K = 1 - d0
             H = K * ((1 - d0) / p["s0"] - (2 - 4 * d0) / r["s2a"] + (1 - 3 * d0) / 2)
             assert np.isclose(r["H"], H, rtol=1e-13)
+        # in the solid core 1 - phi0 is floored at solid_eps (finite H)
         r = orc.macro_node(p, f, 0.5, 0.1, 1.0, 0, 0, 0, 0, 0, 0, 0)
+        nu = 0.1 / (0.5 * p["solid_eps"])
+        assert np.isclose((1 / r["s2a"] - 0.5) * (1 - d0) / 2, nu, rtol=1e-13)
+        assert np.isfinite(r["H"])
+        q = dict(p, solid_eps=1e-9)
+        r = orc.macro_node(q, f, 0.5, 0.1, 1.0, 0, 0, 0, 0, 0, 0, 0)
         assert 0 < r["s2a"] < 1e-4 and 0 < r["s2b"] < 1e-4 and np.isfinite(r["H"])
     # d0 = 1/3: the two relaxation rates coincide
     p = params(1, 1, d0=1 / 3)
