@@ -1,0 +1,190 @@
+"""Benchmark of the coupled D2Q9 phase-field / flow LBM hot path on one MI355X.
+
+A step is one pass of the whole hot path (procedure steps 2-6: stencils,
+velocity and pressure recovery, both MRT collisions, streaming) over the
+1024 x 1024 cylinder + drop workload (density ratio 100, viscosity ratio 50,
+60 degrees, gravity 1e-6), FP32, inputs resident in HBM before timing.
+
+Prints ONE JSON line (metric, value = MLUPS, roofline of the fused step kernel
+from HIP-event timing on its stream, CPU-oracle baseline, extras).
+
+  python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-extra]
+  python bench.py --copy-calibrate      # plain device copy of known size
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBS = 8000.0  # MI355X HBM3E
+# algorithmic bytes per lattice update: 18 populations read + 18 written,
+# previous-level phi, u, S read + written (10 values), static phi0 and psi
+BYTES_PER_LUP = {"fp64": 36 * 8 + 10 * 8 + 2 * 8, "fp32": 36 * 4 + 10 * 4 + 2 * 4,
+                 "fp16dev": 2 * (8 + 8 * 2 + 9 * 2) + 10 * 4 + 2 * 4,
+                 "bf16dev": 2 * (8 + 8 * 2 + 9 * 2) + 10 * 4 + 2 * 4}
+DTYPE = {"fp64": "f64", "fp32": "f32", "fp16dev": "f32 (fp16 storage)", "bf16dev": "f32 (bf16 storage)"}
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_step_c2_fp32.json")
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in ("paper_2311_05097_amd/csrc/lbm_device.h", "paper_2311_05097_amd/csrc/lbm_abi.hip"):
+        h.update(open(os.path.join(ROOT, f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def run_gpu(workload, storage: str, steps: int, warmup: int, tile: int = 0):
+    import torch
+    from paper_2311_05097_amd import lbmgls
+    d = lbmgls.Domain(workload.params, *workload.arrays(), storage=storage, tile=tile)
+    m0 = d.mass()
+    d.step(warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    d.step(steps)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    kernel_ms = d.last_step_ms
+    n = workload.params["nx"] * workload.params["ny"]
+    phi, ux, uy, P = d.read()
+    finite = bool(all(map(lambda a: __import__("numpy").isfinite(a).all(), (phi, ux, uy, P))))
+    import numpy as np
+    drift = abs(d.mass() - m0) / float(np.abs(workload.phi).sum())
+    d.close()
+    return dict(nodes=n, steps=steps, seconds=dt, ms_per_step=1e3 * dt / steps,
+                mlups=n * steps / dt / 1e6, kernel_ms=kernel_ms, mass_drift=drift, finite=finite)
+
+
+def roofline(storage: str, nodes: int, kernel_ms: float, traffic=None):
+    b = BYTES_PER_LUP[storage] * nodes
+    achieved = b / (kernel_ms * 1e-3) / 1e9
+    return {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+            "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": traffic,
+            "bytes_per_lup": BYTES_PER_LUP[storage], "kernel_ms": round(kernel_ms, 5)}
+
+
+def measured_traffic():
+    """HBM bytes per launch from committed rocprofv3 counter runs, if they were
+    taken on the current kernel source."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    t = json.load(open(TRAFFIC_FILE))
+    if t.get("source_hash") != kernel_source_hash():
+        return None
+    return t.get("bytes_per_launch")
+
+
+def cpu_baseline(budget_s: float = 15.0):
+    """The FP64 CPU oracle on the same 1024 x 1024 workload, timed for a
+    bounded number of steps on the host cores."""
+    from oracle import oracle as O
+    from paper_2311_05097_amd import workloads as W
+    O.lib()
+    w = W.config2()
+    t0 = time.perf_counter()
+    o = O.Oracle(w.params, *w.arrays())
+    t_create = time.perf_counter() - t0
+    steps, t0 = 0, time.perf_counter()
+    while True:
+        o.step(1)
+        steps += 1
+        dt = time.perf_counter() - t0
+        if dt > budget_s or steps >= 50:
+            break
+    n = w.params["nx"] * w.params["ny"]
+    return {"value": round(n * steps / dt / 1e6, 4), "unit": "MLUPS", "cores": O.threads(),
+            "kind": "oracle",
+            "sample": f"{steps} steps of the 1024x1024 workload after a {t_create:.1f} s setup, "
+                      f"FP64, {dt:.1f} s"}
+
+
+def copy_calibrate(nbytes: int = 1 << 30, reps: int = 5):
+    import torch
+    a = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda").fill_(1.0)
+    b = torch.empty_like(a)
+    for _ in range(reps):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_read": nbytes, "copy_bytes_written": nbytes, "reps": reps}))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20000)
+    ap.add_argument("--warmup", type=int, default=500)
+    ap.add_argument("--storage", default="fp32", choices=list(BYTES_PER_LUP))
+    ap.add_argument("--tile", type=int, default=0)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-extra", action="store_true")
+    ap.add_argument("--copy-calibrate", action="store_true")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
+              "(the multi-GPU decomposition is design-only)", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    if not torch.cuda.is_available():
+        print("bench.py: no GPU visible", file=sys.stderr)
+        sys.exit(1)
+    torch.cuda.set_device(0)
+    if args.copy_calibrate:
+        copy_calibrate()
+        return
+
+    from paper_2311_05097_amd import workloads as W
+    from paper_2311_05097_amd import autotune
+    w = W.config2()
+    tile = args.tile or autotune.best_tile(w.params, args.storage)
+    r = run_gpu(w, args.storage, args.steps, args.warmup, tile)
+    out = {
+        "metric": "coupled-LBM MLUPS",
+        "value": round(r["mlups"], 2),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(r["ms_per_step"], 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": DTYPE[args.storage],
+        "data": "synthetic (seeded tanh geometry, no dataset)",
+        "config": {"workload": "cylinder+drop 1024x1024 periodic, R_cyl=128, R_drop=160, "
+                               "theta=60, rho ratio 100, mu ratio 50, g=1e-6",
+                   "nx": 1024, "ny": 1024, "storage": args.storage, "tile": f"64x{tile}"},
+        "roofline": roofline(args.storage, r["nodes"], r["kernel_ms"], measured_traffic()),
+        "mass_drift": r["mass_drift"],
+        "finite": r["finite"],
+    }
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline()
+    if not args.no_extra:
+        extra = {}
+        for st in ("fp64", "fp16dev", "bf16dev"):
+            t = autotune.best_tile(w.params, st)
+            e = run_gpu(w, st, 2000, 100, t)
+            extra[f"C2_{st}"] = {"mlups": round(e["mlups"], 1), "tile": t,
+                                 "roofline": roofline(st, e["nodes"], e["kernel_ms"]),
+                                 "mass_drift": e["mass_drift"], "finite": e["finite"]}
+        R = W.roofline_grid()
+        for st in ("fp32", "fp16dev"):
+            t = autotune.best_tile(R.params, st)
+            e = run_gpu(R, st, 300, 20, t)
+            extra[f"R4096_{st}"] = {"mlups": round(e["mlups"], 1), "tile": t,
+                                    "roofline": roofline(st, e["nodes"], e["kernel_ms"]),
+                                    "finite": e["finite"]}
+        out["extra"] = extra
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,176 @@
+/*
+ * lbmgls.h -- C ABI of the MI355X (gfx950) library for the coupled D2Q9
+ * phase-field / flow lattice Boltzmann method of Zhan, Liu, Chai & Shi,
+ * "A thermodynamically consistent and conservative diffuse-interface model
+ * for gas-liquid-solid multiphase flows" (arXiv 2311.05097).
+ *
+ * The library advances, on one GPU, the two sets of D2Q9 distributions of
+ * Sec. 3: g_i for the Cahn-Hilliard phase field (Sec. 3.1; chemical potential
+ * of Eq. (potential) with the solid penalty and wetting terms) and f_i for the
+ * consistent Navier-Stokes flow (Sec. 3.2; viscosity mu/(1-phi0) in the
+ * solid), with the Hermite-moment MRT collision of Sec. 4 and the procedure
+ * of Sec. 3.3 (steps 1-6, stationary solids u_s = 0).  Domains are periodic in
+ * x and y; walls are diffuse solids given through phi0.
+ *
+ * Conventions for every function:
+ *   - return value: LBM_OK (0) or a negative LBM_E* code; nothing throws
+ *     across the ABI; lbm_last_error() gives a message (thread-local).
+ *   - host arrays are row-major [ny][nx] doubles, x fastest, caller-owned;
+ *     they are copied (create) or filled (read) before the call returns.
+ *   - device memory is never allocated by the library: the caller passes a
+ *     device workspace of at least lbm_workspace_bytes() bytes (for example a
+ *     torch uint8 tensor) and keeps it alive until lbm_destroy().  The opaque
+ *     handles themselves are small host allocations.
+ *   - work is enqueued on the HIP stream given at creation (NULL = the null
+ *     stream).  Calls that return host data synchronise that stream.
+ *   - a handle is used by one host thread at a time.
+ */
+#ifndef LBMGLS_H
+#define LBMGLS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    LBM_OK = 0,
+    LBM_EINVAL = -1,       /* bad argument (sizes, parameters, null pointers)    */
+    LBM_ENOMEM = -2,       /* workspace too small                                 */
+    LBM_EDEVICE = -3,      /* a HIP call failed                                   */
+    LBM_ENONFINITE = -4,   /* a NaN/Inf appeared in phi, u or P                   */
+    LBM_EUNSUPPORTED = -5, /* storage / tile option not built                     */
+    LBM_ESTATE = -6        /* handle unusable (after ENONFINITE, or misuse)       */
+};
+
+/* Storage of the distributions.  Arithmetic is FP64 for LBM_STORE_FP64 and
+ * FP32 otherwise.  The *DEV modes keep the eight moving phase-field
+ * populations and all nine flow populations as scaled 16-bit values (their
+ * deviation from the rest-state equilibrium, which is 0 for every moving g_i
+ * and every f_i) and the rest population g_0 as a 64-bit fixed-point number
+ * chosen so that sum_i g_i -- the order parameter -- is conserved exactly. */
+enum {
+    LBM_STORE_FP64 = 0,
+    LBM_STORE_FP32 = 1,
+    LBM_STORE_FP16DEV = 2,
+    LBM_STORE_BF16DEV = 3
+};
+
+/* Tile shapes of the fused step kernel: 64 columns x TY rows. */
+enum { LBM_TILE_AUTO = 0, LBM_TILE_64x4 = 4, LBM_TILE_64x8 = 8, LBM_TILE_64x16 = 16 };
+
+typedef struct {
+    int32_t nx, ny;        /* lattice size, periodic; nx, ny >= 8                  */
+    int32_t storage;       /* LBM_STORE_*                                          */
+    int32_t tile;          /* LBM_TILE_*                                           */
+    double d0;             /* c_s^2 / c^2 in (0, 1); D2Q9 weights (Sec. 4)         */
+    double sigma;          /* sigma_12 > 0 (Eq. 2energyDensity)                    */
+    double D;              /* interface width > 0                                  */
+    double M;              /* mobility > 0 (Eq. CHE)                               */
+    double rho1, rho2;     /* densities of phase 1 (phi = +1) and 2, > 0 (Eq. rho) */
+    double mu1, mu2;       /* dynamic viscosities, > 0                             */
+    double tau_phi;        /* 1/s_{1phi} > 1/2; M = (tau_phi - 1/2) eta c_s^2      */
+    double s0, s1, s2, s3, s4; /* other rates of S_H^1 = diag(s0,s1phi,s1phi,s2,s2,
+                                  s2,s3,s3,s4) and S_H^2 = diag(s0,s1,s1,s2a,s2a,
+                                  s2b,s3,s3,s4), each in (0, 2)                     */
+    double gx, gy, rho_ref;/* body force (rho - rho_ref) g                         */
+    double fbx, fby;       /* body force (1 - phi0) f_b                            */
+    double solid_eps;      /* floor of 1 - phi0 in mu/(rho(1 - phi0)), in (0, 1)   */
+} lbm_params;
+
+typedef struct lbm_domain lbm_domain;
+
+/* Fill *p with the paper's defaults (Sec. 4.1: d0 = 0.4, sigma = 1e-3, D = 4,
+ * M = 0.1, rho = mu-ratio 1, s_i = 1, tau_phi = 1, solid_eps = 0.01) for an
+ * nx x ny grid. */
+void lbm_default_params(lbm_params *p, int32_t nx, int32_t ny);
+
+/* Device bytes a domain with these parameters needs (0 if p is invalid). */
+size_t lbm_workspace_bytes(const lbm_params *p);
+
+/* Procedure step 1 (Sec. 3.3): build the static solid fields from phi0 (the
+ * smooth solid indicator, clamped to [0,1]) and cos_theta (the contact angle
+ * of phase 1 per node; NULL = 90 degrees), compute the chemical potential and
+ * mass flux of the initial phi, and set g = g^eq, f = f^eq with the given
+ * velocity (ux, uy; NULL = 0) and P = 0.  Copies every host array.
+ * dev_workspace: caller-owned device memory of >= lbm_workspace_bytes(p)
+ * bytes, 256-byte aligned.  hip_stream: a hipStream_t or NULL.
+ * Errors: LBM_EINVAL (parameters out of range, non-finite input, null
+ * phi/phi0/out), LBM_ENOMEM (bytes too small), LBM_EDEVICE. */
+int lbm_create(const lbm_params *p, void *dev_workspace, size_t bytes, void *hip_stream,
+               const double *phi, const double *phi0, const double *cos_theta,
+               const double *ux, const double *uy, lbm_domain **out);
+
+/* Procedure steps 2-6, nsteps >= 0 times: one fused kernel per step (stencils
+ * for mu, grad phi, S and F_c from a halo tile, velocity and pressure
+ * recovery, both MRT collisions, streaming).  Enqueued on the stream; returns
+ * without waiting unless a finiteness check is due (lbm_set_check). */
+int lbm_step(lbm_domain *d, int64_t nsteps);
+
+/* Check for NaN/Inf every `every` steps inside lbm_step (0 = never, the
+ * default).  A failed check returns LBM_ENONFINITE and the domain enters
+ * LBM_ESTATE until lbm_import_state(). */
+int lbm_set_check(lbm_domain *d, int64_t every);
+
+/* phi, u = (ux, uy) and P at the current time level (Sec. 3.2, Eqs. phi, u),
+ * each nx*ny doubles; any pointer may be NULL.  Blocks. */
+int lbm_read(lbm_domain *d, double *phi, double *ux, double *uy, double *p);
+
+/* Total order parameter sum phi (FP64 reduction in a fixed order; exact
+ * 64-bit integer sum for the *DEV storage modes).  Blocks. */
+int lbm_mass(lbm_domain *d, double *sum_phi);
+
+/* Discrete free energy E_F of Eq. (2energy) (wetting terms through
+ * psi = cos(theta) phi0) and kinetic energy E_K = sum rho |u|^2 / 2 (Sec. 2.3),
+ * FP64 reductions in a fixed order.  Blocks. */
+int lbm_energy(lbm_domain *d, double *e_free, double *e_kin);
+
+/* Steps taken since lbm_create (or the imported state's count). */
+int64_t lbm_steps_done(const lbm_domain *d);
+
+/* Exact checkpoint: the distributions, the history of the previous level and
+ * the step count.  lbm_state_bytes gives the host buffer size. Blocks. */
+size_t lbm_state_bytes(const lbm_domain *d);
+int lbm_export_state(lbm_domain *d, void *host_buf, size_t bytes);
+int lbm_import_state(lbm_domain *d, const void *host_buf, size_t bytes);
+
+/* Average duration in milliseconds of the fused step kernel over the last
+ * lbm_step call, timed with HIP events on the domain's stream (0 if none). */
+double lbm_last_step_ms(const lbm_domain *d);
+
+/* Release the handle (not the caller's workspace). */
+int lbm_destroy(lbm_domain *d);
+
+/* ---- batching: several domains advanced by one fused launch per step ----
+ * All members share one storage mode.  The batch keeps a device tile table
+ * (one entry per 64 x TY tile of every member) and a member table in a
+ * caller-owned device workspace; each step is ONE kernel launch over all
+ * tiles of all members, and lbm_batch_step captures the steps of a call in a
+ * HIP graph that is replayed while the member set is unchanged. */
+typedef struct lbm_batch lbm_batch;
+
+size_t lbm_batch_workspace_bytes(int32_t max_members, int64_t max_tiles);
+/* hip_stream must be a created (non-null) stream: the steps are captured into
+ * a HIP graph on it, and members must have been created on the same stream. */
+int lbm_batch_create(int32_t storage, int32_t tile, int32_t max_members, int64_t max_tiles,
+                     void *dev_workspace, size_t bytes, void *hip_stream, lbm_batch **out);
+/* Add / remove a domain (created with the same storage mode).  A member may
+ * belong to one batch at a time; removing does not destroy it. */
+int lbm_batch_add(lbm_batch *b, lbm_domain *d);
+int lbm_batch_remove(lbm_batch *b, lbm_domain *d);
+/* Advance every member by min(nsteps, budget) where budget[k] is the number
+ * of steps member k may still take (NULL = nsteps for all).  Enqueued. */
+int lbm_batch_step(lbm_batch *b, int64_t nsteps, const int64_t *budget);
+int lbm_batch_size(const lbm_batch *b);
+int lbm_batch_destroy(lbm_batch *b);
+
+/* Thread-local message describing the last error. */
+const char *lbm_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LBMGLS_H */

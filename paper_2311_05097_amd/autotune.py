@@ -1,0 +1,78 @@
+"""Tile-shape autotuner for the fused step kernel.
+
+The step kernel is compiled for 64 x TY tiles with TY in {4, 8, 16}.  Small TY
+gives more blocks (better load balance on 256 CUs) but recomputes a larger
+share of halo; large TY amortises the 3-node halo of the order parameter.  The
+best choice depends on the grid and on the storage mode, so it is measured:
+each candidate runs a few steps on a scratch domain of the same size and
+storage (HIP-event kernel time), and the fastest is cached in a JSON file
+keyed by (nx, ny, storage).
+
+Cache: $LBMGLS_TUNE_CACHE or ~/.cache/lbmgls/tiles.json.
+"""
+from __future__ import annotations
+
+import json
+import os
+
+import numpy as np
+
+CANDIDATES = (4, 8, 16)
+
+
+def cache_path() -> str:
+    p = os.environ.get("LBMGLS_TUNE_CACHE")
+    if p:
+        return p
+    return os.path.join(os.path.expanduser("~"), ".cache", "lbmgls", "tiles.json")
+
+
+def _load() -> dict:
+    try:
+        with open(cache_path()) as f:
+            return json.load(f)
+    except (OSError, ValueError):
+        return {}
+
+
+def _save(c: dict):
+    p = cache_path()
+    try:
+        os.makedirs(os.path.dirname(p), exist_ok=True)
+        tmp = p + ".tmp"
+        with open(tmp, "w") as f:
+            json.dump(c, f, indent=1, sort_keys=True)
+        os.replace(tmp, p)
+    except OSError:
+        pass
+
+
+def key(nx: int, ny: int, storage: str) -> str:
+    return f"{nx}x{ny}:{storage}"
+
+
+def measure(params: dict, storage: str, ty: int, steps: int = 40, warmup: int = 5) -> float:
+    """Average step-kernel time (ms) of tile shape 64 x ty on a scratch domain."""
+    from . import lbmgls
+    nx, ny = int(params["nx"]), int(params["ny"])
+    y, x = np.mgrid[0:ny, 0:nx].astype(np.float64)
+    phi = np.tanh((min(nx, ny) / 4.0 - np.hypot(x - nx / 2.0, y - ny / 2.0)) / 2.0)
+    d = lbmgls.Domain(params, phi, np.zeros_like(phi), storage=storage, tile=ty)
+    d.step(warmup)
+    d.step(steps)
+    ms = d.last_step_ms
+    d.close()
+    return ms
+
+
+def best_tile(params: dict, storage: str, retune: bool = False) -> int:
+    nx, ny = int(params["nx"]), int(params["ny"])
+    k = key(nx, ny, storage)
+    cache = _load()
+    if not retune and k in cache:
+        return int(cache[k]["tile"])
+    times = {ty: measure(params, storage, ty) for ty in CANDIDATES}
+    best = min(times, key=times.get)
+    cache[k] = {"tile": best, "ms": {str(t): round(v, 5) for t, v in times.items()}}
+    _save(cache)
+    return best

@@ -1,0 +1,707 @@
+// lbm_device.h -- device code for gfx950: the fused per-step kernel of the
+// coupled D2Q9 phase-field / flow lattice Boltzmann method (Zhan, Liu, Chai &
+// Shi, arXiv 2311.05097), its initialisation, read-out and reductions.
+//
+// Data layout in HBM (per domain, N = nx*ny nodes, row pitch nx, x fastest;
+// every array padded to a multiple of 64 nodes, `pitch`):
+//   pop[2]   two copies of the 18 distributions (ping-pong; step n reads
+//            pop[n&1] and writes pop[(n+1)&1]).  Population i of a node is
+//            stored at that node after streaming ("push": a node collides its
+//            own post-stream populations and writes population i to the node
+//            x + c_i of the other copy).
+//   hist[2]  the previous time level phi, ux, uy, Sx, Sy (5 planes), also
+//            ping-pong: step n reads hist[n&1] (level n-1), writes hist[(n+1)&1].
+//   stat     phi0, psi = cos(theta) phi0 and its Laplacian (3 planes, static).
+// Two copies are needed because the step kernel reads, besides each node's own
+// populations, a 3-node halo of the order parameter that neighbouring tiles
+// are updating in the same launch; an in-place (single-copy) update would race.
+//
+// Per step, one launch over 64 x TY tiles (256 threads = 4 wavefronts):
+//   A  phi = sum_i g_i on the tile plus a 3-node halo -> LDS
+//   B  mu (Eq. potential) on tile + 2                 -> LDS
+//   C  S = M (rho1-rho2)/2 grad mu and w = (S x u^{n-1})_z / 2 on tile + 1 -> LDS
+//   D  per node: grad phi, F_c = (-d_y w, d_x w), F, u*, solid force, u, P
+//      (Sec. 3.2), both Hermite-MRT collisions in moment space (Sec. 4), push
+//      of the 18 post-collision values, history write.
+// The same tile code in mode INIT builds the equilibria of procedure step 1,
+// and in mode OUT recovers phi, u, P at the current level and accumulates
+// per-tile FP64 partial sums for mass and energy.
+#pragma once
+#include <stdint.h>
+
+namespace lbm {
+
+constexpr int TX = 64;        // tile width: one wavefront per row
+constexpr int NT = 256;       // threads per block
+constexpr int NWAVE = NT / 64;
+constexpr int NPART = 4;      // partial sums per tile: mass, E_F, E_K, non-finite count
+constexpr int FIX_BITS = 40;  // fixed point of the rest population g_0 (16-bit modes)
+
+enum { MODE_STEP = 0, MODE_OUT = 1, MODE_INIT = 2 };
+
+// Per-domain constants, in the arithmetic type R.
+template <class R>
+struct Coef {
+    R a;                 // c_s^2 = d0 (c = 1)
+    R one_a;             // 1 - d0
+    R w0, w1, w2;        // weights of rest, axis and diagonal directions
+    R inv_n1, inv_n2, inv_n11, inv_n12, inv_n22;  // 1 / Hermite norms
+    R eta;               // M / ((tau_phi - 1/2) d0)
+    R s0, s1, s1phi, s2, s3, s4;
+    R k3s_D;             // 3 sigma / D
+    R k3Ds_8;            // 3 D sigma / 8
+    R k9s_D;             // 9 sigma / D
+    R k3s_4D;            // 3 sigma / (4 D)     (energy)
+    R k3Ds_16;           // 3 D sigma / 16      (energy)
+    R k9s_2D;            // 9 sigma / (2 D)     (energy)
+    R kS;                // M (rho1 - rho2) / 2
+    R drho, srho;        // (rho1 - rho2)/2, (rho1 + rho2)/2
+    R dmu, smu;          // (mu1 - mu2)/2, (mu1 + mu2)/2
+    R gx, gy, rho_ref, fbx, fby;
+    R solid_eps;
+    R ka;                // (c^2 - c_s^2)/2 = (1 - d0)/2
+    R Pfac;              // c_s^2 / (1 - w0)
+    R Pw0;               // w0 / (c^2 - c_s^2)
+    R K2;                // K / 2 = (1 - d0) / 2
+    R Hc0, Hc1;          // H = Hc0 - Hc1 / s2a
+    float sg, isg;       // 16-bit modes: scale of the moving g_i and its inverse
+    float sf, isf;       // 16-bit modes: scale of the f_i
+    float gfix;          // 2^(FIX_BITS) / sg: decoded g code -> fixed point
+};
+
+struct TileEntry {
+    int32_t job, x0, y0, pad;
+};
+
+// ------------------------------------------------------------- storage modes
+struct StF64 {
+    using R = double;
+    struct Pop { double* p; };  // [18][pitch]: g_0..g_8, f_0..f_8
+    static constexpr bool kFix = false;
+    static constexpr int kMode = 0;
+};
+struct StF32 {
+    using R = float;
+    struct Pop { float* p; };
+    static constexpr bool kFix = false;
+    static constexpr int kMode = 1;
+};
+struct StHalfBase {
+    using R = float;
+    // g_0 as 64-bit fixed point, g_1..g_8 and f_0..f_8 as 16-bit codes
+    struct Pop { int64_t* g0; uint16_t* gm; uint16_t* fm; };
+    static constexpr bool kFix = true;
+};
+
+__device__ __forceinline__ uint16_t f16_enc(float v) {
+    _Float16 h = (_Float16)v;  // round to nearest even
+    return __builtin_bit_cast(uint16_t, h);
+}
+__device__ __forceinline__ float f16_dec(uint16_t u) {
+    return (float)__builtin_bit_cast(_Float16, u);
+}
+__device__ __forceinline__ uint16_t bf16_enc(float v) {
+    uint32_t b = __builtin_bit_cast(uint32_t, v);
+    if ((b & 0x7f800000u) == 0x7f800000u && (b & 0x007fffffu))
+        return (uint16_t)((b >> 16) | 0x40u);  // keep NaN a NaN
+    b += 0x7fffu + ((b >> 16) & 1u);           // round to nearest even
+    return (uint16_t)(b >> 16);
+}
+__device__ __forceinline__ float bf16_dec(uint16_t u) {
+    return __builtin_bit_cast(float, (uint32_t)u << 16);
+}
+
+struct StF16 : StHalfBase {
+    static constexpr int kMode = 2;
+    static __device__ __forceinline__ uint16_t enc(float v) { return f16_enc(v); }
+    static __device__ __forceinline__ float dec(uint16_t u) { return f16_dec(u); }
+};
+struct StBF16 : StHalfBase {
+    static constexpr int kMode = 3;
+    static __device__ __forceinline__ uint16_t enc(float v) { return bf16_enc(v); }
+    static __device__ __forceinline__ float dec(uint16_t u) { return bf16_dec(u); }
+};
+
+template <class S>
+struct Job {
+    typename S::Pop pop[2];
+    typename S::R* hist[2];   // [5][pitch]: phi, ux, uy, Sx, Sy of the previous level
+    typename S::R* stat;      // [3][pitch]: phi0, psi, lap psi
+    const double* in;         // INIT: [5][pitch] phi, phi0 (unused), cos (unused), ux, uy
+    double* out;              // OUT: [4][pitch] phi, ux, uy, P (NULL: reductions only)
+    double* part;             // OUT: [ntiles][NPART] partial sums
+    int64_t* ipart;           // OUT, 16-bit modes: [ntiles] exact fixed-point mass
+    int64_t pitch;
+    int64_t step0;            // steps taken before the launch sequence
+    int32_t nx, ny;
+    int32_t n_active;         // launches with t >= n_active leave this job alone
+    int32_t tile_base;        // first tile of this job in the tile table
+    Coef<typename S::R> c;
+};
+
+// ------------------------------------------------------------------ helpers
+__device__ __forceinline__ int wrapi(int v, int n) {
+    v %= n;
+    return v < 0 ? v + n : v;
+}
+
+// Map the hardware block index so that each of the 8 XCDs (blocks are dealt
+// round-robin) gets one contiguous range of tiles: neighbouring tiles, whose
+// halos overlap, then share an L2.
+__device__ __forceinline__ int xcd_remap(int b, int G) {
+    const int q = G >> 3, r = G & 7;
+    const int k = b & 7, j = b >> 3;
+    return k * q + (k < r ? k : r) + j;
+}
+
+// Isotropic central differences (weights 4/9, 1/9, 1/36, c_s^2 = 1/3) on an
+// LDS tile of width W around index q.
+template <class R>
+__device__ __forceinline__ void grad9(const R* s, int q, int W, R& gx, R& gy) {
+    const R e = s[q + 1], w = s[q - 1], n = s[q + W], so = s[q - W];
+    const R ne = s[q + W + 1], nw = s[q + W - 1], se = s[q - W + 1], sw = s[q - W - 1];
+    gx = (e - w) * R(1.0 / 3.0) + ((ne + se) - (nw + sw)) * R(1.0 / 12.0);
+    gy = (n - so) * R(1.0 / 3.0) + ((ne + nw) - (se + sw)) * R(1.0 / 12.0);
+}
+template <class R>
+__device__ __forceinline__ R lap9(const R* s, int q, int W) {
+    const R c4 = R(4) * s[q];
+    const R ax = (s[q + 1] + s[q - 1]) + (s[q + W] + s[q - W]);
+    const R dg = (s[q + W + 1] + s[q + W - 1]) + (s[q - W + 1] + s[q - W - 1]);
+    return (ax - c4) * R(2.0 / 3.0) + (dg - c4) * R(1.0 / 6.0);
+}
+
+template <class R>
+__device__ __forceinline__ R clamp1(R v) {
+    return v < R(-1) ? R(-1) : (v > R(1) ? R(1) : v);
+}
+// Gradient of the order parameter clamped to [-1, 1] (the field the density
+// law is evaluated on).
+template <class R>
+__device__ __forceinline__ void grad9c(const R* s, int q, int W, R& gx, R& gy) {
+    const R e = clamp1(s[q + 1]), w = clamp1(s[q - 1]), n = clamp1(s[q + W]), so = clamp1(s[q - W]);
+    const R ne = clamp1(s[q + W + 1]), nw = clamp1(s[q + W - 1]);
+    const R se = clamp1(s[q - W + 1]), sw = clamp1(s[q - W - 1]);
+    gx = (e - w) * R(1.0 / 3.0) + ((ne + se) - (nw + sw)) * R(1.0 / 12.0);
+    gy = (n - so) * R(1.0 / 3.0) + ((ne + nw) - (se + sw)) * R(1.0 / 12.0);
+}
+
+// Chemical potential, Eq. (potential), wetting terms through psi.
+template <class R>
+__device__ __forceinline__ R chem_pot(const Coef<R>& c, R ph, R lap, R z, R psi, R lpsi) {
+    const R ph2 = ph * ph;
+    return c.k3s_D * (ph * (ph2 - R(1)) + psi * (R(3) * ph2 + z * z - R(1)))
+         + c.k9s_D * z * z * ph - c.k3Ds_8 * (lap + lpsi);
+}
+
+// Hermite moments m_k = sum_i h_k(c_i) f_i of the D2Q9 basis
+// (1, cx, cy, cx^2-a, cy^2-a, cx cy, cx(cy^2-a), cy(cx^2-a), (cx^2-a)(cy^2-a)),
+// computed as a 3x3 tensor transform (x then y).  Velocity order
+// 0:(0,0) 1:(1,0) 2:(0,1) 3:(-1,0) 4:(0,-1) 5:(1,1) 6:(-1,1) 7:(-1,-1) 8:(1,-1).
+template <class R>
+__device__ __forceinline__ void hermite_fwd(const R* f, R a, R one_a, R* m) {
+    const R A00 = (f[3] + f[1]) + f[0], A10 = f[1] - f[3], A20 = one_a * (f[1] + f[3]) - a * f[0];
+    const R A0p = (f[6] + f[5]) + f[2], A1p = f[5] - f[6], A2p = one_a * (f[5] + f[6]) - a * f[2];
+    const R A0m = (f[7] + f[8]) + f[4], A1m = f[8] - f[7], A2m = one_a * (f[8] + f[7]) - a * f[4];
+    m[0] = A00 + (A0p + A0m);
+    m[1] = A10 + (A1p + A1m);
+    m[2] = A0p - A0m;
+    m[3] = A20 + (A2p + A2m);
+    m[4] = one_a * (A0p + A0m) - a * A00;
+    m[5] = A1p - A1m;
+    m[6] = one_a * (A1p + A1m) - a * A10;
+    m[7] = A2p - A2m;
+    m[8] = one_a * (A2p + A2m) - a * A20;
+}
+
+// Inverse transform f_i = w_i sum_k h_k(c_i) m_k / N_k (discrete
+// orthogonality of the Hermite basis under the D2Q9 weights).
+template <class R>
+__device__ __forceinline__ void hermite_inv(const Coef<R>& c, const R* m, R* f) {
+    const R a = c.a, one_a = c.one_a;
+    const R M00 = m[0], M10 = m[1] * c.inv_n1, M01 = m[2] * c.inv_n1;
+    const R M20 = m[3] * c.inv_n2, M02 = m[4] * c.inv_n2, M11 = m[5] * c.inv_n11;
+    const R M12 = m[6] * c.inv_n12, M21 = m[7] * c.inv_n12, M22 = m[8] * c.inv_n22;
+    // y transform: B_j(cy) = sum_k p_k(cy) M_jk, p = (1, c, c^2 - a)
+    const R B00 = M00 - a * M02, B0p = (M00 + M01) + one_a * M02, B0m = (M00 - M01) + one_a * M02;
+    const R B10 = M10 - a * M12, B1p = (M10 + M11) + one_a * M12, B1m = (M10 - M11) + one_a * M12;
+    const R B20 = M20 - a * M22, B2p = (M20 + M21) + one_a * M22, B2m = (M20 - M21) + one_a * M22;
+    f[0] = c.w0 * (B00 - a * B20);
+    f[1] = c.w1 * ((B00 + B10) + one_a * B20);
+    f[3] = c.w1 * ((B00 - B10) + one_a * B20);
+    f[2] = c.w1 * (B0p - a * B2p);
+    f[4] = c.w1 * (B0m - a * B2m);
+    f[5] = c.w2 * ((B0p + B1p) + one_a * B2p);
+    f[6] = c.w2 * ((B0p - B1p) + one_a * B2p);
+    f[7] = c.w2 * ((B0m - B1m) + one_a * B2m);
+    f[8] = c.w2 * ((B0m + B1m) + one_a * B2m);
+}
+
+// ------------------------------------------------------ population access
+template <class S> struct Access;
+
+template <class Sf>
+struct AccessFull {  // FP64 / FP32: plain values
+    using R = typename Sf::R;
+    using Pop = typename Sf::Pop;
+    static __device__ __forceinline__ R phi(const Pop& P, int64_t pitch, int64_t o, const Coef<R>&) {
+        const R* p = P.p + o;
+        return ((p[0] + (p[pitch] + p[3 * pitch])) + (p[2 * pitch] + p[4 * pitch]))
+             + ((p[5 * pitch] + p[7 * pitch]) + (p[6 * pitch] + p[8 * pitch]));
+    }
+    static __device__ __forceinline__ void load(const Pop& P, int64_t pitch, int64_t o, const Coef<R>&,
+                                                R* g, R* f, int64_t& mfix) {
+        const R* p = P.p + o;
+#pragma unroll
+        for (int i = 0; i < 9; ++i) g[i] = p[i * pitch];
+#pragma unroll
+        for (int i = 0; i < 9; ++i) f[i] = p[(9 + i) * pitch];
+        mfix = 0;
+    }
+    static __device__ __forceinline__ void store(const Pop& P, int64_t pitch, const int64_t* dst,
+                                                 const Coef<R>&, const R* g, const R* f, int64_t) {
+#pragma unroll
+        for (int i = 0; i < 9; ++i) P.p[i * pitch + dst[i]] = g[i];
+#pragma unroll
+        for (int i = 0; i < 9; ++i) P.p[(9 + i) * pitch + dst[i]] = f[i];
+    }
+};
+template <> struct Access<StF64> : AccessFull<StF64> {};
+template <> struct Access<StF32> : AccessFull<StF32> {};
+
+template <class Sh>
+struct AccessHalf {  // 16-bit codes + fixed-point rest population
+    using Pop = typename Sh::Pop;
+    static __device__ __forceinline__ int64_t gfix(const Coef<float>& c, uint16_t code) {
+        return (int64_t)llrintf(Sh::dec(code) * c.gfix);
+    }
+    static __device__ __forceinline__ float fix2f(int64_t m) {
+        return (float)m * 0x1p-40f;
+    }
+    static __device__ __forceinline__ float phi(const Pop& P, int64_t pitch, int64_t o, const Coef<float>& c) {
+        int64_t m = P.g0[o];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) m += gfix(c, P.gm[i * pitch + o]);
+        return fix2f(m);
+    }
+    static __device__ __forceinline__ void load(const Pop& P, int64_t pitch, int64_t o, const Coef<float>& c,
+                                                float* g, float* f, int64_t& mfix) {
+        const int64_t rest = P.g0[o];
+        int64_t m = rest;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            const uint16_t code = P.gm[i * pitch + o];
+            g[i + 1] = Sh::dec(code) * c.isg;
+            m += gfix(c, code);
+        }
+        g[0] = fix2f(rest);
+#pragma unroll
+        for (int i = 0; i < 9; ++i) f[i] = Sh::dec(P.fm[i * pitch + o]) * c.isf;
+        mfix = m;
+    }
+    // mfix: the node's conserved sum_i g_i in fixed point; g_0 is written so
+    // that the stored values sum to it exactly.
+    static __device__ __forceinline__ void store(const Pop& P, int64_t pitch, const int64_t* dst,
+                                                 const Coef<float>& c, const float* g, const float* f,
+                                                 int64_t mfix) {
+        int64_t rest = mfix;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            const uint16_t code = Sh::enc(g[i + 1] * c.sg);
+            P.gm[i * pitch + dst[i + 1]] = code;
+            rest -= gfix(c, code);
+        }
+        P.g0[dst[0]] = rest;
+#pragma unroll
+        for (int i = 0; i < 9; ++i) P.fm[i * pitch + dst[i]] = Sh::enc(f[i] * c.sf);
+    }
+};
+template <> struct Access<StF16> : AccessHalf<StF16> {};
+template <> struct Access<StBF16> : AccessHalf<StBF16> {};
+
+// ------------------------------------------------ block reduction (FP64)
+template <class T>
+__device__ __forceinline__ T wave_sum(T v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+// ------------------------------------------------------------ tile kernel
+template <class S, int TY, int MODE>
+__global__ __launch_bounds__(NT) void k_tile(const Job<S>* __restrict__ jobs,
+                                             const TileEntry* __restrict__ tiles, int ntiles, int t) {
+    using R = typename S::R;
+    using A = Access<S>;
+    constexpr int W3 = TX + 6, H3 = TY + 6;
+    constexpr int W2 = TX + 4, H2 = TY + 4;
+    constexpr int W1 = TX + 2, H1 = TY + 2;
+    __shared__ R sphi[H3 * W3];
+    __shared__ R smu[H2 * W2];
+    __shared__ R sSx[H1 * W1];
+    __shared__ R sSy[H1 * W1];
+    __shared__ R sw[H1 * W1];
+    __shared__ double sred[NWAVE][NPART];
+    __shared__ long long sired[NWAVE];
+
+    const int e = xcd_remap((int)blockIdx.x, (int)gridDim.x);
+    if (e >= ntiles) return;
+    const TileEntry te = tiles[e];
+    const Job<S>& J = jobs[te.job];
+    if (MODE == MODE_STEP && t >= J.n_active) return;
+    const int nx = J.nx, ny = J.ny;
+    const int64_t pitch = J.pitch;
+    const int64_t step = J.step0 + (MODE == MODE_STEP ? t : 0);
+    const int par = (int)(step & 1);
+    const bool first = (step == 0);
+    const Coef<R>& c = J.c;
+    const typename S::Pop cur = J.pop[par];
+    const R* __restrict__ hprev = J.hist[par];
+    const R* __restrict__ st = J.stat;
+    const int x0 = te.x0, y0 = te.y0;
+
+    // A: order parameter on the tile and a 3-node halo
+    for (int p = threadIdx.x; p < H3 * W3; p += NT) {
+        const int ly = p / W3, lx = p - ly * W3;
+        const int gx = wrapi(x0 + lx - 3, nx), gy = wrapi(y0 + ly - 3, ny);
+        const int64_t o = (int64_t)gy * nx + gx;
+        if (MODE == MODE_INIT)
+            sphi[p] = (R)J.in[o];
+        else
+            sphi[p] = A::phi(cur, pitch, o, c);
+    }
+    __syncthreads();
+
+    // B: chemical potential on the tile and a 2-node halo
+    for (int p = threadIdx.x; p < H2 * W2; p += NT) {
+        const int ly = p / W2, lx = p - ly * W2;
+        const int gx = wrapi(x0 + lx - 2, nx), gy = wrapi(y0 + ly - 2, ny);
+        const int64_t o = (int64_t)gy * nx + gx;
+        const int q = (ly + 1) * W3 + (lx + 1);
+        smu[p] = chem_pot(c, sphi[q], lap9(sphi, q, W3), st[o], st[pitch + o], st[2 * pitch + o]);
+    }
+    __syncthreads();
+
+    // C: mass flux S and w = (S_x u_y - S_y u_x)/2 with the previous velocity
+    for (int p = threadIdx.x; p < H1 * W1; p += NT) {
+        const int ly = p / W1, lx = p - ly * W1;
+        R gmx, gmy;
+        grad9(smu, (ly + 1) * W2 + (lx + 1), W2, gmx, gmy);
+        const R Sx = c.kS * gmx, Sy = c.kS * gmy;
+        sSx[p] = Sx;
+        sSy[p] = Sy;
+        if (MODE != MODE_INIT) {
+            const int gx = wrapi(x0 + lx - 1, nx), gy = wrapi(y0 + ly - 1, ny);
+            const int64_t o = (int64_t)gy * nx + gx;
+            sw[p] = (Sx * hprev[2 * pitch + o] - Sy * hprev[pitch + o]) * R(0.5);
+        }
+    }
+    __syncthreads();
+
+    // D: node update
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    double acc_m = 0.0, acc_ef = 0.0, acc_ek = 0.0, acc_nf = 0.0;
+    long long acc_im = 0;
+    for (int ly = wv; ly < TY; ly += NWAVE) {
+        const int x = x0 + lane, y = y0 + ly;
+        if (x >= nx || y >= ny) continue;
+        const int64_t o = (int64_t)y * nx + x;
+        const int q3 = (ly + 3) * W3 + (lane + 3);
+        const int q2 = (ly + 2) * W2 + (lane + 2);
+        const int q1 = (ly + 1) * W1 + (lane + 1);
+        const R ph = sphi[q3];
+        R dpx, dpy;
+        grad9(sphi, q3, W3, dpx, dpy);
+        const R mu = smu[q2];
+        const R Sx = sSx[q1], Sy = sSy[q1];
+        const R z = st[o];
+        // density and viscosity laws (Eq. rho) on phi clamped to [-1, 1]
+        const R rho = c.srho + c.drho * clamp1(ph);
+        const R muv = c.smu + c.dmu * clamp1(ph);
+
+        if (MODE == MODE_INIT) {
+            // Procedure step 1: g = g^eq, f = f^eq at P = 0 with the given u.
+            const R ux = (R)J.in[3 * pitch + o], uy = (R)J.in[4 * pitch + o];
+            // g^eq of Sec. 3.1, term by term (keeps the small moving values exact)
+            const R emu = c.eta * mu, ia = R(1) / c.a;
+            const R jxa = ph * ux * ia, jya = ph * uy * ia;
+            R m[9], g[9], f[9];
+            g[0] = ph + (c.w0 - R(1)) * emu;
+            g[1] = c.w1 * (emu + jxa);
+            g[3] = c.w1 * (emu - jxa);
+            g[2] = c.w1 * (emu + jya);
+            g[4] = c.w1 * (emu - jya);
+            g[5] = c.w2 * (emu + (jxa + jya));
+            g[6] = c.w2 * (emu + (jya - jxa));
+            g[7] = c.w2 * (emu - (jxa + jya));
+            g[8] = c.w2 * (emu + (jxa - jya));
+            m[0] = R(0); m[1] = rho * ux; m[2] = rho * uy;
+            m[3] = rho * ux * ux - Sx * ux; m[4] = rho * uy * uy - Sy * uy;
+            m[5] = rho * ux * uy - (Sx * uy + ux * Sy) * R(0.5);
+            m[6] = R(0); m[7] = R(0); m[8] = R(0);
+            hermite_inv(c, m, f);
+            int64_t dst[9];
+#pragma unroll
+            for (int i = 0; i < 9; ++i) dst[i] = o;
+            int64_t mfix = 0;
+            if (S::kFix) mfix = llrint(J.in[o] * 0x1p40);
+            A::store(J.pop[0], pitch, dst, c, g, f, mfix);
+            R* h0 = J.hist[0];
+            h0[o] = ph; h0[pitch + o] = ux; h0[2 * pitch + o] = uy;
+            h0[3 * pitch + o] = Sx; h0[4 * pitch + o] = Sy;
+            continue;
+        }
+
+        R wx, wy;
+        grad9(sw, q1, W1, wx, wy);
+        R dcx, dcy;
+        grad9c(sphi, q3, W3, dcx, dcy);
+        const R drx = c.drho * dcx, dry = c.drho * dcy;
+        // total force F = mu grad phi + F_b + F_c, F_c = (-d_y w, d_x w)
+        const R Fx = mu * dpx + ((rho - c.rho_ref) * c.gx + (R(1) - z) * c.fbx) - wy;
+        const R Fy = mu * dpy + ((rho - c.rho_ref) * c.gy + (R(1) - z) * c.fby) + wx;
+
+        R g[9], f[9];
+        int64_t mfix;
+        A::load(cur, pitch, o, c, g, f, mfix);
+        const R php = hprev[o], uxp = hprev[pitch + o], uyp = hprev[2 * pitch + o];
+        const R Sxp = hprev[3 * pitch + o], Syp = hprev[4 * pitch + o];
+
+        // Eq. uStar, solid forcing f = phi0 (u_s - u*), Eq. u (u_s = 0)
+        R usx, usy;
+        if (first) {
+            usx = uxp;
+            usy = uyp;
+        } else {
+            const R jx = ((f[1] - f[3]) + (f[5] - f[6])) + (f[8] - f[7]);
+            const R jy = ((f[2] - f[4]) + (f[5] + f[6])) - (f[7] + f[8]);
+            const R irho = R(1) / rho;
+            usx = (jx + R(0.5) * Fx) * irho;
+            usy = (jy + R(0.5) * Fy) * irho;
+        }
+        const R ax = -z * usx, ay = -z * usy;
+        const R ux = first ? usx : usx + R(0.5) * ax;
+        const R uy = first ? usy : usy + R(0.5) * ay;
+        // flow relaxation from mu/(rho (1 - phi0)), kept finite in the solid
+        R one_m = R(1) - z;
+        one_m = one_m < c.solid_eps ? c.solid_eps : one_m;
+        const R nu = muv / (rho * one_m);
+        const R tau_a = nu / c.ka + R(0.5);
+        const R tau_b = nu / c.a + R(0.5);
+        const R s2a = R(1) / tau_a, s2b = R(1) / tau_b;
+        const R udr = ux * drx + uy * dry;
+        const R q = rho * (ux * ux + uy * uy) - (Sx * ux + Sy * uy);
+        const R rhop = c.srho + c.drho * clamp1(php);
+        const R qp = rhop * (uxp * uxp + uyp * uyp) - (Sxp * uxp + Syp * uyp);
+        R P = R(0);
+        if (!first) {
+            const R H = c.Hc0 - c.Hc1 * tau_a;
+            const R sum = ((f[1] + f[3]) + (f[2] + f[4])) + ((f[5] + f[7]) + (f[6] + f[8]));
+            P = c.Pfac * (sum + (R(0.5) + H) * udr
+                          - c.Pw0 * ((rho * ux - Sx) * ux + (rho * uy - Sy) * uy) + c.K2 * (q - qp));
+        }
+
+        if (MODE == MODE_OUT) {
+            if (J.out) {
+                J.out[o] = (double)ph;
+                J.out[pitch + o] = (double)ux;
+                J.out[2 * pitch + o] = (double)uy;
+                J.out[3 * pitch + o] = (double)P;
+            }
+            // energy densities (Eq. 2energy with psi; e_K = rho |u|^2 / 2)
+            R qx = 0, qy = 0;
+            {
+                const int xe = x + 1 == nx ? 0 : x + 1, xw = x == 0 ? nx - 1 : x - 1;
+                const int yn = y + 1 == ny ? 0 : y + 1, ys = y == 0 ? ny - 1 : y - 1;
+                const R* psi = st + pitch;
+                const int64_t rn = (int64_t)yn * nx, rc = (int64_t)y * nx, rs = (int64_t)ys * nx;
+                const R e_ = psi[rc + xe], w_ = psi[rc + xw], n_ = psi[rn + x], s_ = psi[rs + x];
+                const R ne = psi[rn + xe], nw = psi[rn + xw], se = psi[rs + xe], sw_ = psi[rs + xw];
+                qx = (e_ - w_) * R(1.0 / 3.0) + ((ne + se) - (nw + sw_)) * R(1.0 / 12.0);
+                qy = (n_ - s_) * R(1.0 / 3.0) + ((ne + nw) - (se + sw_)) * R(1.0 / 12.0);
+            }
+            const R psi0 = st[pitch + o];
+            const R om = R(1) - ph * ph;
+            const R ef = c.k3s_4D * om * om + c.k3Ds_16 * (dpx * dpx + dpy * dpy)
+                       + c.k9s_2D * z * z * ph * ph + c.k3s_D * psi0 * ph * (ph * ph + z * z - R(1))
+                       + R(2) * c.k3Ds_16 * (qx * dpx + qy * dpy);
+            const R ek = R(0.5) * rho * (ux * ux + uy * uy);
+            acc_m += (double)ph;
+            acc_ef += (double)ef;
+            acc_ek += (double)ek;
+            if (S::kFix) acc_im += (long long)mfix;
+            const bool bad = !(ph == ph && ux == ux && uy == uy && P == P) ||
+                             !(ph - ph == R(0) && ux - ux == R(0) && uy - uy == R(0) && P - P == R(0));
+            acc_nf += bad ? 1.0 : 0.0;
+            continue;
+        }
+
+        // ---- phase field collision (Sec. 3.1, Hermite MRT) ----
+        // Done as g* = g + M_H^{-1} dm with dm = -S (m - m^eq) + (I - S/2) m^G.
+        // The non-equilibrium moments m - m^eq are formed from raw moments of
+        // the eight moving populations only (the O(1) order parameter carried
+        // by g_0 cancels analytically), so the small moving populations keep
+        // their relative precision in FP32.
+        const R a = c.a, one_a = c.one_a;
+        R m[9];
+        {
+            const R jx = (g[1] - g[3]) + ((g[5] - g[6]) + (g[8] - g[7]));
+            const R jy = (g[2] - g[4]) + ((g[5] + g[6]) - (g[7] + g[8]));
+            const R dsum = (g[5] + g[6]) + (g[7] + g[8]);
+            const R Pxx = (g[1] + g[3]) + dsum, Pyy = (g[2] + g[4]) + dsum;
+            const R Pxy = (g[5] + g[7]) - (g[6] + g[8]);
+            const R Qxyy = (g[5] + g[8]) - (g[6] + g[7]);
+            const R Qxxy = (g[5] + g[6]) - (g[7] + g[8]);
+            const R aem = a * c.eta * mu;
+            const R Vx = ph * ux - php * uxp, Vy = ph * uy - php * uyp;  // d_t(phi u)
+            const R kG = R(1) - R(0.5) * c.s1phi;
+            m[0] = R(0);
+            m[1] = kG * Vx - c.s1phi * (jx - ph * ux);
+            m[2] = kG * Vy - c.s1phi * (jy - ph * uy);
+            m[3] = -c.s2 * (Pxx - aem);
+            m[4] = -c.s2 * (Pyy - aem);
+            m[5] = -c.s2 * Pxy;
+            m[6] = -c.s3 * (Qxyy - a * jx);
+            m[7] = -c.s3 * (Qxxy - a * jy);
+            m[8] = -c.s4 * ((dsum - a * (Pxx + Pyy)) + a * aem);
+            R corr[9];
+            hermite_inv(c, m, corr);
+#pragma unroll
+            for (int i = 0; i < 9; ++i) g[i] += corr[i];
+        }
+
+        // ---- flow collision (Sec. 3.2, Hermite MRT, per-node s2a, s2b) ----
+        hermite_fwd(f, a, one_a, m);
+        {
+            const R Txx = Sx * ux, Tyy = Sy * uy, Txy = R(0.5) * (Sx * uy + ux * Sy);
+            const R Txxp = Sxp * uxp, Tyyp = Syp * uyp, Txyp = R(0.5) * (Sxp * uyp + uxp * Syp);
+            const R c3 = R(1) - R(3) * a;
+            const R M2xx = R(2) * ux * Fx - (Txx - Txxp) + R(2) * a * ux * drx + c3 * udr;
+            const R M2yy = R(2) * uy * Fy - (Tyy - Tyyp) + R(2) * a * uy * dry + c3 * udr;
+            const R M2xy = (ux * Fy + Fx * uy) - (Txy - Txyp) + a * (ux * dry + drx * uy);
+            const R Fpx = Fx + rho * ax, Fpy = Fy + rho * ay;
+            const R rux = rho * ux, ruy = rho * uy;
+            m[0] = m[0] - c.s0 * m[0] + (R(1) - R(0.5) * c.s0) * udr;
+            m[1] = m[1] - c.s1 * (m[1] - rux) + (R(1) - R(0.5) * c.s1) * Fpx;
+            m[2] = m[2] - c.s1 * (m[2] - ruy) + (R(1) - R(0.5) * c.s1) * Fpy;
+            m[3] = m[3] - s2a * (m[3] - (P + rux * ux - Sx * ux)) + (R(1) - R(0.5) * s2a) * M2xx;
+            m[4] = m[4] - s2a * (m[4] - (P + ruy * uy - Sy * uy)) + (R(1) - R(0.5) * s2a) * M2yy;
+            m[5] = m[5] - s2b * (m[5] - (rux * uy - R(0.5) * (Sx * uy + ux * Sy)))
+                 + (R(1) - R(0.5) * s2b) * M2xy;
+            m[6] = m[6] - c.s3 * m[6];
+            m[7] = m[7] - c.s3 * m[7];
+            m[8] = m[8] - c.s4 * (m[8] + a * P);
+        }
+        hermite_inv(c, m, f);
+
+        // ---- push to the other copy, periodic ----
+        const int xe = x + 1 == nx ? 0 : x + 1, xw = x == 0 ? nx - 1 : x - 1;
+        const int64_t rc = (int64_t)y * nx;
+        const int64_t rn = (int64_t)(y + 1 == ny ? 0 : y + 1) * nx;
+        const int64_t rs = (int64_t)(y == 0 ? ny - 1 : y - 1) * nx;
+        int64_t dst[9];
+        dst[0] = o;
+        dst[1] = rc + xe;
+        dst[2] = rn + x;
+        dst[3] = rc + xw;
+        dst[4] = rs + x;
+        dst[5] = rn + xe;
+        dst[6] = rn + xw;
+        dst[7] = rs + xw;
+        dst[8] = rs + xe;
+        A::store(J.pop[par ^ 1], pitch, dst, c, g, f, mfix);
+        R* hn = J.hist[par ^ 1];
+        hn[o] = ph;
+        hn[pitch + o] = ux;
+        hn[2 * pitch + o] = uy;
+        hn[3 * pitch + o] = Sx;
+        hn[4 * pitch + o] = Sy;
+    }
+
+    if (MODE == MODE_OUT) {
+        acc_m = wave_sum(acc_m);
+        acc_ef = wave_sum(acc_ef);
+        acc_ek = wave_sum(acc_ek);
+        acc_nf = wave_sum(acc_nf);
+        acc_im = wave_sum(acc_im);
+        if (lane == 0) {
+            sred[wv][0] = acc_m;
+            sred[wv][1] = acc_ef;
+            sred[wv][2] = acc_ek;
+            sred[wv][3] = acc_nf;
+            sired[wv] = acc_im;
+        }
+        __syncthreads();
+        if (threadIdx.x < NPART) {
+            const int k = threadIdx.x;
+            const double s = ((sred[0][k] + sred[1][k]) + (sred[2][k] + sred[3][k]));
+            J.part[(int64_t)(e - J.tile_base) * NPART + k] = s;
+        }
+        if (S::kFix && threadIdx.x == NPART)
+            J.ipart[e - J.tile_base] = (sired[0] + sired[1]) + (sired[2] + sired[3]);
+    }
+}
+
+// ---------------------------------------------------------- static fields
+// phi0 clamped to [0, 1], psi = cos(theta) phi0 (input staging planes 1, 2).
+template <class R>
+__global__ __launch_bounds__(NT) void k_static(const double* __restrict__ in, R* __restrict__ st,
+                                               int64_t pitch, int64_t n) {
+    const int64_t o = (int64_t)blockIdx.x * NT + threadIdx.x;
+    if (o >= n) return;
+    double z = in[pitch + o];
+    z = z < 0.0 ? 0.0 : (z > 1.0 ? 1.0 : z);
+    st[o] = (R)z;
+    st[pitch + o] = (R)(in[2 * pitch + o] * z);
+}
+
+// Laplacian of psi (static wetting field), periodic.
+template <class R>
+__global__ __launch_bounds__(NT) void k_lap_psi(R* __restrict__ st, int64_t pitch, int nx, int ny) {
+    const int64_t o = (int64_t)blockIdx.x * NT + threadIdx.x;
+    if (o >= (int64_t)nx * ny) return;
+    const int y = (int)(o / nx), x = (int)(o - (int64_t)y * nx);
+    const R* psi = st + pitch;
+    const int xe = x + 1 == nx ? 0 : x + 1, xw = x == 0 ? nx - 1 : x - 1;
+    const int64_t rc = (int64_t)y * nx, rn = (int64_t)(y + 1 == ny ? 0 : y + 1) * nx;
+    const int64_t rs = (int64_t)(y == 0 ? ny - 1 : y - 1) * nx;
+    const R c4 = R(4) * psi[o];
+    const R ax = (psi[rc + xe] + psi[rc + xw]) + (psi[rn + x] + psi[rs + x]);
+    const R dg = (psi[rn + xe] + psi[rn + xw]) + (psi[rs + xe] + psi[rs + xw]);
+    st[2 * pitch + o] = (ax - c4) * R(2.0 / 3.0) + (dg - c4) * R(1.0 / 6.0);
+}
+
+// Fixed-order sum of the per-tile partials: res[k] = sum_i part[i][k],
+// res[NPART] = exact fixed-point mass (16-bit modes) as a double-rounded value
+// and ires[0] its 64-bit integer.
+__global__ __launch_bounds__(NT) void k_final_sum(const double* __restrict__ part,
+                                                  const int64_t* __restrict__ ipart, int ntiles,
+                                                  double* __restrict__ res, int64_t* __restrict__ ires) {
+    __shared__ double s[NT][NPART];
+    __shared__ long long si[NT];
+    double acc[NPART] = {0.0, 0.0, 0.0, 0.0};
+    long long ai = 0;
+    for (int i = threadIdx.x; i < ntiles; i += NT) {
+#pragma unroll
+        for (int k = 0; k < NPART; ++k) acc[k] += part[(int64_t)i * NPART + k];
+        if (ipart) ai += ipart[i];
+    }
+#pragma unroll
+    for (int k = 0; k < NPART; ++k) s[threadIdx.x][k] = acc[k];
+    si[threadIdx.x] = ai;
+    __syncthreads();
+    for (int h = NT / 2; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h) {
+#pragma unroll
+            for (int k = 0; k < NPART; ++k) s[threadIdx.x][k] += s[threadIdx.x + h][k];
+            si[threadIdx.x] += si[threadIdx.x + h];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        for (int k = 0; k < NPART; ++k) res[k] = s[0][k];
+        ires[0] = si[0];
+    }
+}
+
+}  // namespace lbm

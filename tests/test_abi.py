@@ -1,0 +1,72 @@
+"""The C-ABI library loads and exports every function include/lbmgls.h
+declares, and the binding's struct layout matches the header (CPU only: no
+compute call is made)."""
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "lbmgls.h")
+
+
+def _lib():
+    from paper_2311_05097_amd import lbmgls
+    if not os.path.exists(lbmgls.LIB_PATH):
+        from paper_2311_05097_amd import build
+        build.build()
+    return lbmgls
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(lbm_[a-z_]+)\s*\(", text)))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for must in ("lbm_create", "lbm_step", "lbm_read", "lbm_mass", "lbm_energy", "lbm_destroy",
+                 "lbm_batch_step"):
+        assert must in names
+
+
+def test_library_exports_every_declared_symbol():
+    lbmgls = _lib()
+    L = ctypes.CDLL(lbmgls.LIB_PATH)
+    missing = [n for n in declared_functions() if not hasattr(L, n)]
+    assert not missing, missing
+    assert sorted(lbmgls.EXPORTED) == declared_functions()
+
+
+def test_params_layout_matches_header(tmp_path):
+    lbmgls = _lib()
+    fields = [f for f, _ in lbmgls.LbmParams._fields_]
+    src = tmp_path / "lay.c"
+    body = "\n".join(f'printf("{f} %zu\\n", offsetof(lbm_params, {f}));' for f in fields)
+    src.write_text(f'#include <stdio.h>\n#include <stddef.h>\n#include "lbmgls.h"\n'
+                   f'int main(void){{printf("size %zu\\n", sizeof(lbm_params));{body}return 0;}}\n')
+    exe = tmp_path / "lay"
+    subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), "-o", str(exe), str(src)])
+    out = dict(line.split() for line in subprocess.check_output([str(exe)]).decode().splitlines())
+    assert int(out["size"]) == ctypes.sizeof(lbmgls.LbmParams)
+    for f in fields:
+        assert int(out[f]) == getattr(lbmgls.LbmParams, f).offset, f
+
+
+def test_workspace_size_and_validation_host_only():
+    lbmgls = _lib()
+    from paper_2311_05097_amd import workloads as W
+    w = W.config1()
+    n32 = lbmgls.workspace_bytes(w.params, "fp32")
+    n64 = lbmgls.workspace_bytes(w.params, "fp64")
+    n16 = lbmgls.workspace_bytes(w.params, "fp16dev")
+    assert n16 < n32 < n64
+    N = 64 * 64
+    assert n32 >= 2 * 18 * 4 * N + 2 * 5 * 4 * N + 3 * 4 * N
+    with pytest.raises(lbmgls.LbmError):
+        lbmgls.workspace_bytes(dict(w.params, nx=4), "fp32")
+    with pytest.raises(lbmgls.LbmError):
+        lbmgls.workspace_bytes(dict(w.params, d0=1.2), "fp32")
