@@ -115,6 +115,75 @@ def copy_calibrate(nbytes: int = 1 << 30, reps: int = 5):
     print(json.dumps({"copy_bytes_read": nbytes, "copy_bytes_written": nbytes, "reps": reps}))
 
 
+def serve_bench(args):
+    """Served jobs/s and p50/p99 latency of the drop-on-slab job stream:
+    plain FP32 per-job path versus continuous batching in FP32, FP16 and BF16
+    storage, on the same seeded stream and arrival times."""
+    import numpy as np
+    from paper_2311_05097_amd import lbmgls, serve
+    from paper_2311_05097_amd import workloads as W
+    lo, hi = args.ratio_range
+    base = W.job_stream(n_jobs=args.jobs, seed=4, ratio_range=(lo, hi))
+    # plain FP32 capacity from a short solo run, arrivals at twice that rate
+    probe = W.JobSpec(0, 512, 90.0, 10.0, 400).workload()
+    d = lbmgls.Domain(probe.params, *probe.arrays(), storage="fp32", tile=8)
+    d.step(20)
+    d.step(300)
+    glups = 512 * 512 / (d.last_step_ms * 1e-3) / 1e9
+    d.close()
+    mean_lups = float(np.mean([j.side ** 2 * j.steps for j in base]))
+    capacity = glups * 1e9 / mean_lups
+    rate = args.rate_factor * capacity
+    jobs = W.job_stream(n_jobs=args.jobs, seed=4, ratio_range=(lo, hi), rate_per_s=rate)
+    ref_ids = {j.job_id for j in jobs[:: args.ref_every]}
+    refs = {}
+    for j in jobs:
+        if j.job_id in ref_ids:
+            w = j.workload()
+            r = lbmgls.Domain(w.params, *w.arrays(), storage="fp64", tile=8)
+            r.set_check(1000)
+            try:
+                r.step(j.steps)
+                refs[j.job_id] = r.read()[0]
+            except lbmgls.LbmError:
+                pass
+            r.close()
+    modes = []
+    runs = [("solo", "fp32")] + [("batched", s) for s in ("fp32", "fp16dev", "bf16dev")]
+    for kind, st in runs:
+        if kind == "solo":
+            stats = serve.run_solo(jobs, storage=st, tile=8, keep_phi=True)
+        else:
+            srv = serve.Server(storage=st, budget_bytes=args.budget_gib << 30, tick_steps=args.tick,
+                               tile=8, keep_phi=True)
+            stats = srv.run(jobs)
+            srv.close()
+        s = stats.summary()
+        errs = [float(np.linalg.norm(j.phi - refs[j.job_id]) / np.linalg.norm(refs[j.job_id]))
+                for j in stats.jobs if j.status == "done" and j.job_id in refs and j.phi is not None]
+        s["max_rel_phi_err_vs_fp64"] = max(errs) if errs else None
+        s["phi_err_jobs"] = len(errs)
+        modes.append(s)
+        print(json.dumps(s), file=sys.stderr, flush=True)
+    best = max((m for m in modes if m["mode"] != "solo-fp32"), key=lambda m: m["jobs_per_s"] or 0)
+    solo = modes[0]
+    out = {
+        "metric": "served jobs/s",
+        "value": best["jobs_per_s"],
+        "unit": "jobs/s",
+        "n_gpus": 1,
+        "higher_is_better": True,
+        "vs_plain_fp32_per_job": round(best["jobs_per_s"] / solo["jobs_per_s"], 3) if solo["jobs_per_s"] else None,
+        "data": "synthetic seeded job stream (drop on slab)",
+        "config": {"workload": f"{args.jobs} drop-on-slab jobs, side in 128..1024, theta U[30,150], "
+                               f"density ratio U[{lo:g},{hi:g}], steps U[2000,20000], Poisson arrivals at "
+                               f"{args.rate_factor:g}x the plain FP32 capacity ({rate:.2f} jobs/s)",
+                   "budget_GiB": args.budget_gib, "tick_steps": args.tick, "best_mode": best["mode"]},
+        "modes": modes,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -125,6 +194,16 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extra", action="store_true")
     ap.add_argument("--copy-calibrate", action="store_true")
+    ap.add_argument("--workload", default="c2", choices=["c2", "r4096"],
+                    help="c2: the 1024^2 cylinder + drop case (default); r4096: the same physics "
+                         "on 4096^2 (working set far above the last-level cache)")
+    ap.add_argument("--serve", action="store_true", help="served-jobs benchmark instead")
+    ap.add_argument("--jobs", type=int, default=256)
+    ap.add_argument("--ratio-range", type=float, nargs=2, default=(10.0, 1000.0))
+    ap.add_argument("--rate-factor", type=float, default=2.0)
+    ap.add_argument("--budget-gib", type=int, default=4)
+    ap.add_argument("--tick", type=int, default=500)
+    ap.add_argument("--ref-every", type=int, default=8)
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -139,10 +218,13 @@ def main():
     if args.copy_calibrate:
         copy_calibrate()
         return
+    if args.serve:
+        serve_bench(args)
+        return
 
     from paper_2311_05097_amd import workloads as W
     from paper_2311_05097_amd import autotune
-    w = W.config2()
+    w = W.config2() if args.workload == "c2" else W.roofline_grid()
     tile = args.tile or autotune.best_tile(w.params, args.storage)
     r = run_gpu(w, args.storage, args.steps, args.warmup, tile)
     out = {
@@ -158,9 +240,10 @@ def main():
         "vs_baseline": None,
         "dtype": DTYPE[args.storage],
         "data": "synthetic (seeded tanh geometry, no dataset)",
-        "config": {"workload": "cylinder+drop 1024x1024 periodic, R_cyl=128, R_drop=160, "
-                               "theta=60, rho ratio 100, mu ratio 50, g=1e-6",
-                   "nx": 1024, "ny": 1024, "storage": args.storage, "tile": f"64x{tile}"},
+        "config": {"workload": w.name + ": periodic, cylinder R=%g, drop R=%g, theta=60, "
+                               "rho ratio 100, mu ratio 50, g=1e-6" % (w.meta["Rp"], w.meta["R0"]),
+                   "nx": w.params["nx"], "ny": w.params["ny"], "storage": args.storage,
+                   "tile": f"64x{tile}"},
         "roofline": roofline(args.storage, r["nodes"], r["kernel_ms"], measured_traffic()),
         "mass_drift": r["mass_drift"],
         "finite": r["finite"],

@@ -58,8 +58,9 @@ enum {
     LBM_STORE_BF16DEV = 3
 };
 
-/* Tile shapes of the fused step kernel: 64 columns x TY rows. */
-enum { LBM_TILE_AUTO = 0, LBM_TILE_64x4 = 4, LBM_TILE_64x8 = 8, LBM_TILE_64x16 = 16 };
+/* Tile shapes of the fused step kernel: 64 columns x TY rows (256 threads for
+ * TY <= 8, 512 for TY >= 16; 64x32 is not built for FP64). */
+enum { LBM_TILE_AUTO = 0, LBM_TILE_64x4 = 4, LBM_TILE_64x8 = 8, LBM_TILE_64x16 = 16, LBM_TILE_64x32 = 32 };
 
 typedef struct {
     int32_t nx, ny;        /* lattice size, periodic; nx, ny >= 8                  */
@@ -113,6 +114,11 @@ int lbm_step(lbm_domain *d, int64_t nsteps);
  * default).  A failed check returns LBM_ENONFINITE and the domain enters
  * LBM_ESTATE until lbm_import_state(). */
 int lbm_set_check(lbm_domain *d, int64_t every);
+
+/* Finiteness check of phi, u and P at the current level (one fused pass over
+ * the domain).  Returns LBM_OK, or LBM_ENONFINITE and the domain enters
+ * LBM_ESTATE.  Blocks. */
+int lbm_check(lbm_domain *d);
 
 /* phi, u = (ux, uy) and P at the current time level (Sec. 3.2, Eqs. phi, u),
  * each nx*ny doubles; any pointer may be NULL.  Blocks. */

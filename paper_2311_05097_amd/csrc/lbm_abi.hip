@@ -63,6 +63,7 @@ size_t job_size(int storage) {
 
 int pick_ty(const lbm_params& p) {
     if (p.tile == LBM_TILE_64x4 || p.tile == LBM_TILE_64x8 || p.tile == LBM_TILE_64x16) return p.tile;
+    if (p.tile == LBM_TILE_64x32 && p.storage != LBM_STORE_FP64) return p.tile;
     // default: 64 x 8 (the autotuner in the Python layer overrides per shape)
     return 8;
 }
@@ -72,12 +73,14 @@ bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
 int validate(const lbm_params* p) {
     if (!p) return fail(LBM_EINVAL, "params is NULL");
     if (p->nx < 8 || p->ny < 8) return fail(LBM_EINVAL, "nx and ny must be >= 8");
-    if ((int64_t)p->nx * p->ny > (int64_t)1 << 31) return fail(LBM_EINVAL, "domain too large");
+    if ((int64_t)p->nx * p->ny >= (int64_t)1 << 31) return fail(LBM_EINVAL, "domain too large (2^31 nodes)");
     if (p->storage < LBM_STORE_FP64 || p->storage > LBM_STORE_BF16DEV)
         return fail(LBM_EUNSUPPORTED, "unknown storage mode");
     if (!(p->tile == LBM_TILE_AUTO || p->tile == LBM_TILE_64x4 || p->tile == LBM_TILE_64x8 ||
-          p->tile == LBM_TILE_64x16))
+          p->tile == LBM_TILE_64x16 || p->tile == LBM_TILE_64x32))
         return fail(LBM_EUNSUPPORTED, "unknown tile shape");
+    if (p->tile == LBM_TILE_64x32 && p->storage == LBM_STORE_FP64)
+        return fail(LBM_EUNSUPPORTED, "64x32 tiles are not built for FP64 (LDS)");
     if (!(p->d0 > 0.0 && p->d0 < 1.0)) return fail(LBM_EINVAL, "d0 must lie in (0, 1)");
     if (!finite_pos(p->sigma) || !finite_pos(p->D) || !finite_pos(p->M))
         return fail(LBM_EINVAL, "sigma, D and M must be positive");
@@ -234,7 +237,7 @@ template <class S, int TY, int MODE>
 int launch_tiles(lbm_domain* d, int t) {
     const Job<S>* J = (const Job<S>*)(d->ws + d->L.off_job);
     const TileEntry* T = (const TileEntry*)(d->ws + d->L.off_tiles);
-    hipLaunchKernelGGL((k_tile<S, TY, MODE>), dim3(d->L.ntiles), dim3(NT), 0, d->stream, J, T,
+    hipLaunchKernelGGL((k_tile<S, TY, MODE>), dim3(d->L.ntiles), dim3(TileCfg<TY>::NT), 0, d->stream, J, T,
                        d->L.ntiles, t);
     HIPCHK(hipGetLastError());
     return LBM_OK;
@@ -245,6 +248,9 @@ int launch_tiles_ty(lbm_domain* d, int t) {
     switch (d->L.ty) {
         case 4: return launch_tiles<S, 4, MODE>(d, t);
         case 16: return launch_tiles<S, 16, MODE>(d, t);
+        case 32:
+            if constexpr (sizeof(typename S::R) == 4) return launch_tiles<S, 32, MODE>(d, t);
+            return fail(LBM_EUNSUPPORTED, "64x32 tiles are not built for FP64");
         default: return launch_tiles<S, 8, MODE>(d, t);
     }
 }
@@ -428,6 +434,9 @@ int lbm_create(const lbm_params* p, void* dev_workspace, size_t bytes, void* hip
     d->stream = (hipStream_t)hip_stream;
     d->ws = (char*)dev_workspace;
     d->job.resize(job_size(p->storage));
+    // Row-major tile order: the tiles running at the same time cover long
+    // contiguous stretches of each row (measured faster than a column-major
+    // order, whose 64-wide strips stride through memory at the row pitch).
     for (int ty = 0; ty < L.tiles_y; ++ty)
         for (int tx = 0; tx < L.tiles_x; ++tx) d->tiles.push_back(TileEntry{0, tx * TX, ty * L.ty, 0});
     if (hipEventCreate(&d->ev0) != hipSuccess || hipEventCreate(&d->ev1) != hipSuccess) {
@@ -457,6 +466,21 @@ int lbm_set_check(lbm_domain* d, int64_t every) {
     if (every < 0) return fail(LBM_EINVAL, "every must be >= 0");
     d->check_every = every;
     return LBM_OK;
+}
+
+int lbm_check(lbm_domain* d) {
+    int rc = usable(d);
+    if (rc) return rc;
+    return dispatch(d->p.storage, [&](auto s) -> int {
+        double res[NPART];
+        int r = reduce<decltype(s)>(d, false, res, nullptr);
+        if (r) return r;
+        if (res[3] > 0.0) {
+            d->failed = true;
+            return fail(LBM_ENONFINITE, "non-finite phi, u or P at step " + std::to_string(d->steps));
+        }
+        return LBM_OK;
+    });
 }
 
 int lbm_read(lbm_domain* d, double* phi, double* ux, double* uy, double* P) {
@@ -582,7 +606,8 @@ int batch_capture(lbm_batch* b, int64_t nsteps) {
     HIPCHK(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
     hipError_t le = hipSuccess;
     for (int64_t t = 0; t < nsteps && le == hipSuccess; ++t) {
-        hipLaunchKernelGGL((k_tile<S, TY, MODE_STEP>), dim3(nt), dim3(NT), 0, b->stream, J, T, nt, (int)t);
+        hipLaunchKernelGGL((k_tile<S, TY, MODE_STEP>), dim3(nt), dim3(TileCfg<TY>::NT), 0, b->stream, J, T, nt,
+                           (int)t);
         le = hipGetLastError();
     }
     hipError_t ce = hipStreamEndCapture(b->stream, &b->graph);  // always leave capture mode
@@ -630,6 +655,12 @@ int batch_step_impl(lbm_batch* b, int64_t nsteps, const int64_t* budget) {
         switch (b->ty) {
             case 4: rc = batch_capture<S, 4>(b, nsteps); break;
             case 16: rc = batch_capture<S, 16>(b, nsteps); break;
+            case 32:
+                if constexpr (sizeof(typename S::R) == 4) {
+                    rc = batch_capture<S, 32>(b, nsteps);
+                    break;
+                }
+                return fail(LBM_EUNSUPPORTED, "64x32 tiles are not built for FP64");
             default: rc = batch_capture<S, 8>(b, nsteps); break;
         }
         if (rc) return rc;
@@ -655,7 +686,9 @@ int lbm_batch_create(int32_t storage, int32_t tile, int32_t max_members, int64_t
     if (!out) return fail(LBM_EINVAL, "out is NULL");
     *out = nullptr;
     if (storage < LBM_STORE_FP64 || storage > LBM_STORE_BF16DEV) return fail(LBM_EUNSUPPORTED, "unknown storage");
-    if (!(tile == LBM_TILE_AUTO || tile == 4 || tile == 8 || tile == 16)) return fail(LBM_EUNSUPPORTED, "unknown tile");
+    if (!(tile == LBM_TILE_AUTO || tile == 4 || tile == 8 || tile == 16 || tile == 32))
+        return fail(LBM_EUNSUPPORTED, "unknown tile");
+    if (tile == 32 && storage == LBM_STORE_FP64) return fail(LBM_EUNSUPPORTED, "64x32 tiles are not built for FP64");
     if (max_members <= 0 || max_tiles <= 0) return fail(LBM_EINVAL, "sizes must be positive");
     if (!dev_workspace || (uintptr_t)dev_workspace % ALIGN) return fail(LBM_EINVAL, "workspace NULL or unaligned");
     if (bytes < lbm_batch_workspace_bytes(max_members, max_tiles)) return fail(LBM_ENOMEM, "workspace too small");

@@ -238,27 +238,35 @@ __device__ __forceinline__ void hermite_inv(const Coef<R>& c, const R* m, R* f) 
 }
 
 // ------------------------------------------------------ population access
+// Node offsets are 32-bit (domains hold fewer than 2^31 nodes); each plane
+// base is a uniform pointer, so loads use a scalar base plus a 32-bit vector
+// offset.
 template <class S> struct Access;
 
 template <class Sf>
 struct AccessFull {  // FP64 / FP32: plain values
     using R = typename Sf::R;
     using Pop = typename Sf::Pop;
-    static __device__ __forceinline__ R phi(const Pop& P, int64_t pitch, int64_t o, const Coef<R>&) {
-        const R* p = P.p + o;
-        return ((p[0] + (p[pitch] + p[3 * pitch])) + (p[2 * pitch] + p[4 * pitch]))
-             + ((p[5 * pitch] + p[7 * pitch]) + (p[6 * pitch] + p[8 * pitch]));
+    static __device__ __forceinline__ R phi(const Pop& P, int64_t pitch, uint32_t o, const Coef<R>&) {
+        const R* p = P.p;
+        return ((p[o] + (p[pitch + o] + p[3 * pitch + o])) + (p[2 * pitch + o] + p[4 * pitch + o]))
+             + ((p[5 * pitch + o] + p[7 * pitch + o]) + (p[6 * pitch + o] + p[8 * pitch + o]));
     }
-    static __device__ __forceinline__ void load(const Pop& P, int64_t pitch, int64_t o, const Coef<R>&,
-                                                R* g, R* f, int64_t& mfix) {
-        const R* p = P.p + o;
+    static __device__ __forceinline__ void load_g(const Pop& P, int64_t pitch, uint32_t o, const Coef<R>&,
+                                                  R* g, int64_t& mfix) {
 #pragma unroll
-        for (int i = 0; i < 9; ++i) g[i] = p[i * pitch];
-#pragma unroll
-        for (int i = 0; i < 9; ++i) f[i] = p[(9 + i) * pitch];
+        for (int i = 0; i < 9; ++i) g[i] = P.p[i * pitch + o];
         mfix = 0;
     }
-    static __device__ __forceinline__ void store(const Pop& P, int64_t pitch, const int64_t* dst,
+    static __device__ __forceinline__ R phi_of(const R* g, int64_t, const Coef<R>&) {
+        return ((g[0] + (g[1] + g[3])) + (g[2] + g[4])) + ((g[5] + g[7]) + (g[6] + g[8]));
+    }
+    static __device__ __forceinline__ void load_f(const Pop& P, int64_t pitch, uint32_t o, const Coef<R>&,
+                                                  R* f) {
+#pragma unroll
+        for (int i = 0; i < 9; ++i) f[i] = P.p[(9 + i) * pitch + o];
+    }
+    static __device__ __forceinline__ void store(const Pop& P, int64_t pitch, const uint32_t* dst,
                                                  const Coef<R>&, const R* g, const R* f, int64_t) {
 #pragma unroll
         for (int i = 0; i < 9; ++i) P.p[i * pitch + dst[i]] = g[i];
@@ -278,14 +286,14 @@ struct AccessHalf {  // 16-bit codes + fixed-point rest population
     static __device__ __forceinline__ float fix2f(int64_t m) {
         return (float)m * 0x1p-40f;
     }
-    static __device__ __forceinline__ float phi(const Pop& P, int64_t pitch, int64_t o, const Coef<float>& c) {
+    static __device__ __forceinline__ float phi(const Pop& P, int64_t pitch, uint32_t o, const Coef<float>& c) {
         int64_t m = P.g0[o];
 #pragma unroll
         for (int i = 0; i < 8; ++i) m += gfix(c, P.gm[i * pitch + o]);
         return fix2f(m);
     }
-    static __device__ __forceinline__ void load(const Pop& P, int64_t pitch, int64_t o, const Coef<float>& c,
-                                                float* g, float* f, int64_t& mfix) {
+    static __device__ __forceinline__ void load_g(const Pop& P, int64_t pitch, uint32_t o, const Coef<float>& c,
+                                                  float* g, int64_t& mfix) {
         const int64_t rest = P.g0[o];
         int64_t m = rest;
 #pragma unroll
@@ -295,13 +303,19 @@ struct AccessHalf {  // 16-bit codes + fixed-point rest population
             m += gfix(c, code);
         }
         g[0] = fix2f(rest);
+        mfix = m;
+    }
+    static __device__ __forceinline__ float phi_of(const float*, int64_t mfix, const Coef<float>&) {
+        return fix2f(mfix);
+    }
+    static __device__ __forceinline__ void load_f(const Pop& P, int64_t pitch, uint32_t o, const Coef<float>& c,
+                                                  float* f) {
 #pragma unroll
         for (int i = 0; i < 9; ++i) f[i] = Sh::dec(P.fm[i * pitch + o]) * c.isf;
-        mfix = m;
     }
     // mfix: the node's conserved sum_i g_i in fixed point; g_0 is written so
     // that the stored values sum to it exactly.
-    static __device__ __forceinline__ void store(const Pop& P, int64_t pitch, const int64_t* dst,
+    static __device__ __forceinline__ void store(const Pop& P, int64_t pitch, const uint32_t* dst,
                                                  const Coef<float>& c, const float* g, const float* f,
                                                  int64_t mfix) {
         int64_t rest = mfix;
@@ -328,21 +342,43 @@ __device__ __forceinline__ T wave_sum(T v) {
 }
 
 // ------------------------------------------------------------ tile kernel
+// Block size per tile height: 256 threads (4 wavefronts) for 64 x 4 and
+// 64 x 8 tiles, 512 (8 wavefronts) for 64 x 16 and 64 x 32.
+template <int TY>
+struct TileCfg {
+    static constexpr int NT = TY >= 16 ? 512 : 256;
+};
+
+// Thread (lane, wave) owns the nodes (x0 + lane, y0 + wave + NW k), k < NOWN.
+// All global reads a block needs beyond its own nodes -- the order parameter
+// on the 3-node halo ring, the static fields on the 2-node halo, the previous
+// velocity on the 1-node halo -- are issued in one phase (A) before the first
+// barrier, so their latencies overlap.
 template <class S, int TY, int MODE>
-__global__ __launch_bounds__(NT) void k_tile(const Job<S>* __restrict__ jobs,
-                                             const TileEntry* __restrict__ tiles, int ntiles, int t) {
+__global__ __launch_bounds__(TileCfg<TY>::NT) void k_tile(const Job<S>* __restrict__ jobs,
+                                                         const TileEntry* __restrict__ tiles, int ntiles,
+                                                         int t) {
     using R = typename S::R;
     using A = Access<S>;
+    constexpr int NTH = TileCfg<TY>::NT;
+    constexpr int NW = NTH / 64;
     constexpr int W3 = TX + 6, H3 = TY + 6;
     constexpr int W2 = TX + 4, H2 = TY + 4;
     constexpr int W1 = TX + 2, H1 = TY + 2;
+    constexpr int NOWN = TY / NW;                 // owned nodes per thread
+    constexpr bool KEEP = NOWN <= 2;              // keep owned data in registers from phase A
+    constexpr int NRING = 6 * W3 + 6 * TY;        // halo ring of the order parameter
+    constexpr int NB = (H2 * W2 + NTH - 1) / NTH; // stage-B points per thread
+    constexpr int NC = (H1 * W1 + NTH - 1) / NTH; // stage-C points per thread
     __shared__ R sphi[H3 * W3];
     __shared__ R smu[H2 * W2];
     __shared__ R sSx[H1 * W1];
     __shared__ R sSy[H1 * W1];
     __shared__ R sw[H1 * W1];
-    __shared__ double sred[NWAVE][NPART];
-    __shared__ long long sired[NWAVE];
+    __shared__ int s_col[W3];                     // periodic x of LDS column lx (x0 + lx - 3)
+    __shared__ int s_row[H3];                     // periodic y * nx of LDS row ly (y0 + ly - 3)
+    __shared__ double sred[NW][NPART];
+    __shared__ long long sired[NW];
 
     const int e = xcd_remap((int)blockIdx.x, (int)gridDim.x);
     if (e >= ntiles) return;
@@ -359,53 +395,160 @@ __global__ __launch_bounds__(NT) void k_tile(const Job<S>* __restrict__ jobs,
     const R* __restrict__ hprev = J.hist[par];
     const R* __restrict__ st = J.stat;
     const int x0 = te.x0, y0 = te.y0;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
 
-    // A: order parameter on the tile and a 3-node halo
-    for (int p = threadIdx.x; p < H3 * W3; p += NT) {
-        const int ly = p / W3, lx = p - ly * W3;
-        const int gx = wrapi(x0 + lx - 3, nx), gy = wrapi(y0 + ly - 3, ny);
-        const int64_t o = (int64_t)gy * nx + gx;
-        if (MODE == MODE_INIT)
-            sphi[p] = (R)J.in[o];
+    // periodic index tables (the only integer divisions of the kernel)
+    for (int i = tid; i < W3 + H3; i += NTH) {
+        if (i < W3)
+            s_col[i] = wrapi(x0 + i - 3, nx);
         else
-            sphi[p] = A::phi(cur, pitch, o, c);
+            s_row[i - W3] = wrapi(y0 + (i - W3) - 3, ny) * nx;
     }
     __syncthreads();
 
-    // B: chemical potential on the tile and a 2-node halo
-    for (int p = threadIdx.x; p < H2 * W2; p += NT) {
-        const int ly = p / W2, lx = p - ly * W2;
-        const int gx = wrapi(x0 + lx - 2, nx), gy = wrapi(y0 + ly - 2, ny);
-        const int64_t o = (int64_t)gy * nx + gx;
-        const int q = (ly + 1) * W3 + (lx + 1);
-        smu[p] = chem_pot(c, sphi[q], lap9(sphi, q, W3), st[o], st[pitch + o], st[2 * pitch + o]);
+    // ---- phase A: every global read ----
+    R g[KEEP ? NOWN : 1][9], f[KEEP ? NOWN : 1][9], hp[KEEP ? NOWN : 1][5];
+    int64_t mfix[KEEP ? NOWN : 1];
+    R zz[NOWN];
+    uint32_t own[NOWN];
+#pragma unroll
+    for (int k = 0; k < NOWN; ++k) {
+        const int ly = wv + NW * k;
+        const uint32_t o = (uint32_t)(s_row[ly + 3] + s_col[lane + 3]);
+        own[k] = o;
+        R* sp = &sphi[(ly + 3) * W3 + lane + 3];
+        if (MODE == MODE_INIT) {
+            *sp = (R)J.in[o];
+        } else if (KEEP) {
+            const int kk = KEEP ? k : 0;
+            A::load_g(cur, pitch, o, c, g[kk], mfix[kk]);
+            A::load_f(cur, pitch, o, c, f[kk]);
+#pragma unroll
+            for (int v = 0; v < 5; ++v) hp[kk][v] = hprev[v * pitch + o];
+            *sp = A::phi_of(g[kk], mfix[kk], c);
+        } else {
+            *sp = A::phi(cur, pitch, o, c);
+        }
+        zz[k] = st[o];
     }
-    __syncthreads();
-
-    // C: mass flux S and w = (S_x u_y - S_y u_x)/2 with the previous velocity
-    for (int p = threadIdx.x; p < H1 * W1; p += NT) {
-        const int ly = p / W1, lx = p - ly * W1;
-        R gmx, gmy;
-        grad9(smu, (ly + 1) * W2 + (lx + 1), W2, gmx, gmy);
-        const R Sx = c.kS * gmx, Sy = c.kS * gmy;
-        sSx[p] = Sx;
-        sSy[p] = Sy;
-        if (MODE != MODE_INIT) {
-            const int gx = wrapi(x0 + lx - 1, nx), gy = wrapi(y0 + ly - 1, ny);
-            const int64_t o = (int64_t)gy * nx + gx;
-            sw[p] = (Sx * hprev[2 * pitch + o] - Sy * hprev[pitch + o]) * R(0.5);
+    for (int p = tid; p < NRING; p += NTH) {
+        int ly, lx;
+        if (p < 3 * W3) {
+            ly = p / W3; lx = p - ly * W3;
+        } else if (p < 6 * W3) {
+            const int q = p - 3 * W3;
+            ly = TY + 3 + q / W3; lx = q - (q / W3) * W3;
+        } else {
+            const int q = p - 6 * W3;
+            const int r = q / 6, cc = q - r * 6;
+            ly = 3 + r; lx = cc < 3 ? cc : TX + cc;
+        }
+        const uint32_t o = (uint32_t)(s_row[ly] + s_col[lx]);
+        if (MODE == MODE_INIT)
+            sphi[ly * W3 + lx] = (R)J.in[o];
+        else
+            sphi[ly * W3 + lx] = A::phi(cur, pitch, o, c);
+    }
+    // static fields on the stage-B points and previous velocity on the
+    // stage-C points, held in registers until those stages
+    R bz[NB], bpsi[NB], blp[NB], cux[NC], cuy[NC];
+#pragma unroll
+    for (int k = 0; k < NB; ++k) {
+        const int p = tid + k * NTH;
+        if (p < H2 * W2) {
+            const int ly = p / W2, lx = p - ly * W2;
+            const uint32_t o = (uint32_t)(s_row[ly + 1] + s_col[lx + 1]);
+            bz[k] = st[o];
+            bpsi[k] = st[pitch + o];
+            blp[k] = st[2 * pitch + o];
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < NC; ++k) {
+        const int p = tid + k * NTH;
+        cux[k] = R(0);
+        cuy[k] = R(0);
+        if (MODE != MODE_INIT && p < H1 * W1) {
+            const int ly = p / W1, lx = p - ly * W1;
+            const uint32_t o = (uint32_t)(s_row[ly + 2] + s_col[lx + 2]);
+            cux[k] = hprev[pitch + o];
+            cuy[k] = hprev[2 * pitch + o];
         }
     }
     __syncthreads();
 
-    // D: node update
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    // ---- B: chemical potential on the tile and a 2-node halo ----
+#pragma unroll
+    for (int k = 0; k < NB; ++k) {
+        const int p = tid + k * NTH;
+        if (p < H2 * W2) {
+            const int ly = p / W2, lx = p - ly * W2;
+            const int q = (ly + 1) * W3 + (lx + 1);
+            smu[p] = chem_pot(c, sphi[q], lap9(sphi, q, W3), bz[k], bpsi[k], blp[k]);
+        }
+    }
+    __syncthreads();
+
+    // ---- C: mass flux S and w = (S_x u_y - S_y u_x)/2 with the previous velocity ----
+#pragma unroll
+    for (int k = 0; k < NC; ++k) {
+        const int p = tid + k * NTH;
+        if (p < H1 * W1) {
+            const int ly = p / W1, lx = p - ly * W1;
+            R gmx, gmy;
+            grad9(smu, (ly + 1) * W2 + (lx + 1), W2, gmx, gmy);
+            const R Sx = c.kS * gmx, Sy = c.kS * gmy;
+            sSx[p] = Sx;
+            sSy[p] = Sy;
+            if (MODE != MODE_INIT) sw[p] = (Sx * cuy[k] - Sy * cux[k]) * R(0.5);
+        }
+    }
+    __syncthreads();
+
+    // ---- D: node update ----
     double acc_m = 0.0, acc_ef = 0.0, acc_ek = 0.0, acc_nf = 0.0;
     long long acc_im = 0;
-    for (int ly = wv; ly < TY; ly += NWAVE) {
+    // owned data for the node being updated (prefetched one node ahead when
+    // it is not kept from phase A)
+    R gn[9], fn[9], hn[5];
+    int64_t mn = 0;
+    if (!KEEP && MODE != MODE_INIT) {
+        A::load_g(cur, pitch, own[0], c, gn, mn);
+        A::load_f(cur, pitch, own[0], c, fn);
+#pragma unroll
+        for (int v = 0; v < 5; ++v) hn[v] = hprev[v * pitch + own[0]];
+    }
+#pragma unroll
+    for (int k = 0; k < NOWN; ++k) {
+        R gk[9], fk[9], hk[5];
+        int64_t mk = 0;
+        if (MODE != MODE_INIT) {
+            if (KEEP) {
+                const int kk = KEEP ? k : 0;
+#pragma unroll
+                for (int i = 0; i < 9; ++i) { gk[i] = g[kk][i]; fk[i] = f[kk][i]; }
+#pragma unroll
+                for (int v = 0; v < 5; ++v) hk[v] = hp[kk][v];
+                mk = mfix[kk];
+            } else {
+#pragma unroll
+                for (int i = 0; i < 9; ++i) { gk[i] = gn[i]; fk[i] = fn[i]; }
+#pragma unroll
+                for (int v = 0; v < 5; ++v) hk[v] = hn[v];
+                mk = mn;
+                if (k + 1 < NOWN) {
+                    const uint32_t o1 = own[k + 1 < NOWN ? k + 1 : k];
+                    A::load_g(cur, pitch, o1, c, gn, mn);
+                    A::load_f(cur, pitch, o1, c, fn);
+#pragma unroll
+                    for (int v = 0; v < 5; ++v) hn[v] = hprev[v * pitch + o1];
+                }
+            }
+        }
+        const int ly = wv + NW * k;
         const int x = x0 + lane, y = y0 + ly;
         if (x >= nx || y >= ny) continue;
-        const int64_t o = (int64_t)y * nx + x;
+        const uint32_t o = own[k];
         const int q3 = (ly + 3) * W3 + (lane + 3);
         const int q2 = (ly + 2) * W2 + (lane + 2);
         const int q1 = (ly + 1) * W1 + (lane + 1);
@@ -414,10 +557,15 @@ __global__ __launch_bounds__(NT) void k_tile(const Job<S>* __restrict__ jobs,
         grad9(sphi, q3, W3, dpx, dpy);
         const R mu = smu[q2];
         const R Sx = sSx[q1], Sy = sSy[q1];
-        const R z = st[o];
+        const R z = zz[k];
         // density and viscosity laws (Eq. rho) on phi clamped to [-1, 1]
         const R rho = c.srho + c.drho * clamp1(ph);
         const R muv = c.smu + c.dmu * clamp1(ph);
+        // neighbours for the push (periodic)
+        const int xe = x + 1 == nx ? 0 : x + 1, xw = x == 0 ? nx - 1 : x - 1;
+        const uint32_t rc = (uint32_t)y * (uint32_t)nx;
+        const uint32_t rn = (uint32_t)(y + 1 == ny ? 0 : y + 1) * (uint32_t)nx;
+        const uint32_t rs = (uint32_t)(y == 0 ? ny - 1 : y - 1) * (uint32_t)nx;
 
         if (MODE == MODE_INIT) {
             // Procedure step 1: g = g^eq, f = f^eq at P = 0 with the given u.
@@ -425,27 +573,27 @@ __global__ __launch_bounds__(NT) void k_tile(const Job<S>* __restrict__ jobs,
             // g^eq of Sec. 3.1, term by term (keeps the small moving values exact)
             const R emu = c.eta * mu, ia = R(1) / c.a;
             const R jxa = ph * ux * ia, jya = ph * uy * ia;
-            R m[9], g[9], f[9];
-            g[0] = ph + (c.w0 - R(1)) * emu;
-            g[1] = c.w1 * (emu + jxa);
-            g[3] = c.w1 * (emu - jxa);
-            g[2] = c.w1 * (emu + jya);
-            g[4] = c.w1 * (emu - jya);
-            g[5] = c.w2 * (emu + (jxa + jya));
-            g[6] = c.w2 * (emu + (jya - jxa));
-            g[7] = c.w2 * (emu - (jxa + jya));
-            g[8] = c.w2 * (emu + (jxa - jya));
+            R m[9], gg[9], ff[9];
+            gg[0] = ph + (c.w0 - R(1)) * emu;
+            gg[1] = c.w1 * (emu + jxa);
+            gg[3] = c.w1 * (emu - jxa);
+            gg[2] = c.w1 * (emu + jya);
+            gg[4] = c.w1 * (emu - jya);
+            gg[5] = c.w2 * (emu + (jxa + jya));
+            gg[6] = c.w2 * (emu + (jya - jxa));
+            gg[7] = c.w2 * (emu - (jxa + jya));
+            gg[8] = c.w2 * (emu + (jxa - jya));
             m[0] = R(0); m[1] = rho * ux; m[2] = rho * uy;
             m[3] = rho * ux * ux - Sx * ux; m[4] = rho * uy * uy - Sy * uy;
             m[5] = rho * ux * uy - (Sx * uy + ux * Sy) * R(0.5);
             m[6] = R(0); m[7] = R(0); m[8] = R(0);
-            hermite_inv(c, m, f);
-            int64_t dst[9];
+            hermite_inv(c, m, ff);
+            uint32_t dst[9];
 #pragma unroll
             for (int i = 0; i < 9; ++i) dst[i] = o;
-            int64_t mfix = 0;
-            if (S::kFix) mfix = llrint(J.in[o] * 0x1p40);
-            A::store(J.pop[0], pitch, dst, c, g, f, mfix);
+            int64_t mf = 0;
+            if (S::kFix) mf = llrint(J.in[o] * 0x1p40);
+            A::store(J.pop[0], pitch, dst, c, gg, ff, mf);
             R* h0 = J.hist[0];
             h0[o] = ph; h0[pitch + o] = ux; h0[2 * pitch + o] = uy;
             h0[3 * pitch + o] = Sx; h0[4 * pitch + o] = Sy;
@@ -460,12 +608,7 @@ __global__ __launch_bounds__(NT) void k_tile(const Job<S>* __restrict__ jobs,
         // total force F = mu grad phi + F_b + F_c, F_c = (-d_y w, d_x w)
         const R Fx = mu * dpx + ((rho - c.rho_ref) * c.gx + (R(1) - z) * c.fbx) - wy;
         const R Fy = mu * dpy + ((rho - c.rho_ref) * c.gy + (R(1) - z) * c.fby) + wx;
-
-        R g[9], f[9];
-        int64_t mfix;
-        A::load(cur, pitch, o, c, g, f, mfix);
-        const R php = hprev[o], uxp = hprev[pitch + o], uyp = hprev[2 * pitch + o];
-        const R Sxp = hprev[3 * pitch + o], Syp = hprev[4 * pitch + o];
+        const R php = hk[0], uxp = hk[1], uyp = hk[2], Sxp = hk[3], Syp = hk[4];
 
         // Eq. uStar, solid forcing f = phi0 (u_s - u*), Eq. u (u_s = 0)
         R usx, usy;
@@ -473,8 +616,8 @@ __global__ __launch_bounds__(NT) void k_tile(const Job<S>* __restrict__ jobs,
             usx = uxp;
             usy = uyp;
         } else {
-            const R jx = ((f[1] - f[3]) + (f[5] - f[6])) + (f[8] - f[7]);
-            const R jy = ((f[2] - f[4]) + (f[5] + f[6])) - (f[7] + f[8]);
+            const R jx = ((fk[1] - fk[3]) + (fk[5] - fk[6])) + (fk[8] - fk[7]);
+            const R jy = ((fk[2] - fk[4]) + (fk[5] + fk[6])) - (fk[7] + fk[8]);
             const R irho = R(1) / rho;
             usx = (jx + R(0.5) * Fx) * irho;
             usy = (jy + R(0.5) * Fy) * irho;
@@ -496,7 +639,7 @@ __global__ __launch_bounds__(NT) void k_tile(const Job<S>* __restrict__ jobs,
         R P = R(0);
         if (!first) {
             const R H = c.Hc0 - c.Hc1 * tau_a;
-            const R sum = ((f[1] + f[3]) + (f[2] + f[4])) + ((f[5] + f[7]) + (f[6] + f[8]));
+            const R sum = ((fk[1] + fk[3]) + (fk[2] + fk[4])) + ((fk[5] + fk[7]) + (fk[6] + fk[8]));
             P = c.Pfac * (sum + (R(0.5) + H) * udr
                           - c.Pw0 * ((rho * ux - Sx) * ux + (rho * uy - Sy) * uy) + c.K2 * (q - qp));
         }
@@ -509,12 +652,9 @@ __global__ __launch_bounds__(NT) void k_tile(const Job<S>* __restrict__ jobs,
                 J.out[3 * pitch + o] = (double)P;
             }
             // energy densities (Eq. 2energy with psi; e_K = rho |u|^2 / 2)
-            R qx = 0, qy = 0;
+            R qx, qy;
             {
-                const int xe = x + 1 == nx ? 0 : x + 1, xw = x == 0 ? nx - 1 : x - 1;
-                const int yn = y + 1 == ny ? 0 : y + 1, ys = y == 0 ? ny - 1 : y - 1;
                 const R* psi = st + pitch;
-                const int64_t rn = (int64_t)yn * nx, rc = (int64_t)y * nx, rs = (int64_t)ys * nx;
                 const R e_ = psi[rc + xe], w_ = psi[rc + xw], n_ = psi[rn + x], s_ = psi[rs + x];
                 const R ne = psi[rn + xe], nw = psi[rn + xw], se = psi[rs + xe], sw_ = psi[rs + xw];
                 qx = (e_ - w_) * R(1.0 / 3.0) + ((ne + se) - (nw + sw_)) * R(1.0 / 12.0);
@@ -529,7 +669,7 @@ __global__ __launch_bounds__(NT) void k_tile(const Job<S>* __restrict__ jobs,
             acc_m += (double)ph;
             acc_ef += (double)ef;
             acc_ek += (double)ek;
-            if (S::kFix) acc_im += (long long)mfix;
+            if (S::kFix) acc_im += (long long)mk;
             const bool bad = !(ph == ph && ux == ux && uy == uy && P == P) ||
                              !(ph - ph == R(0) && ux - ux == R(0) && uy - uy == R(0) && P - P == R(0));
             acc_nf += bad ? 1.0 : 0.0;
@@ -545,13 +685,13 @@ __global__ __launch_bounds__(NT) void k_tile(const Job<S>* __restrict__ jobs,
         const R a = c.a, one_a = c.one_a;
         R m[9];
         {
-            const R jx = (g[1] - g[3]) + ((g[5] - g[6]) + (g[8] - g[7]));
-            const R jy = (g[2] - g[4]) + ((g[5] + g[6]) - (g[7] + g[8]));
-            const R dsum = (g[5] + g[6]) + (g[7] + g[8]);
-            const R Pxx = (g[1] + g[3]) + dsum, Pyy = (g[2] + g[4]) + dsum;
-            const R Pxy = (g[5] + g[7]) - (g[6] + g[8]);
-            const R Qxyy = (g[5] + g[8]) - (g[6] + g[7]);
-            const R Qxxy = (g[5] + g[6]) - (g[7] + g[8]);
+            const R jx = (gk[1] - gk[3]) + ((gk[5] - gk[6]) + (gk[8] - gk[7]));
+            const R jy = (gk[2] - gk[4]) + ((gk[5] + gk[6]) - (gk[7] + gk[8]));
+            const R dsum = (gk[5] + gk[6]) + (gk[7] + gk[8]);
+            const R Pxx = (gk[1] + gk[3]) + dsum, Pyy = (gk[2] + gk[4]) + dsum;
+            const R Pxy = (gk[5] + gk[7]) - (gk[6] + gk[8]);
+            const R Qxyy = (gk[5] + gk[8]) - (gk[6] + gk[7]);
+            const R Qxxy = (gk[5] + gk[6]) - (gk[7] + gk[8]);
             const R aem = a * c.eta * mu;
             const R Vx = ph * ux - php * uxp, Vy = ph * uy - php * uyp;  // d_t(phi u)
             const R kG = R(1) - R(0.5) * c.s1phi;
@@ -567,11 +707,11 @@ __global__ __launch_bounds__(NT) void k_tile(const Job<S>* __restrict__ jobs,
             R corr[9];
             hermite_inv(c, m, corr);
 #pragma unroll
-            for (int i = 0; i < 9; ++i) g[i] += corr[i];
+            for (int i = 0; i < 9; ++i) gk[i] += corr[i];
         }
 
         // ---- flow collision (Sec. 3.2, Hermite MRT, per-node s2a, s2b) ----
-        hermite_fwd(f, a, one_a, m);
+        hermite_fwd(fk, a, one_a, m);
         {
             const R Txx = Sx * ux, Tyy = Sy * uy, Txy = R(0.5) * (Sx * uy + ux * Sy);
             const R Txxp = Sxp * uxp, Tyyp = Syp * uyp, Txyp = R(0.5) * (Sxp * uyp + uxp * Syp);
@@ -592,14 +732,10 @@ __global__ __launch_bounds__(NT) void k_tile(const Job<S>* __restrict__ jobs,
             m[7] = m[7] - c.s3 * m[7];
             m[8] = m[8] - c.s4 * (m[8] + a * P);
         }
-        hermite_inv(c, m, f);
+        hermite_inv(c, m, fk);
 
         // ---- push to the other copy, periodic ----
-        const int xe = x + 1 == nx ? 0 : x + 1, xw = x == 0 ? nx - 1 : x - 1;
-        const int64_t rc = (int64_t)y * nx;
-        const int64_t rn = (int64_t)(y + 1 == ny ? 0 : y + 1) * nx;
-        const int64_t rs = (int64_t)(y == 0 ? ny - 1 : y - 1) * nx;
-        int64_t dst[9];
+        uint32_t dst[9];
         dst[0] = o;
         dst[1] = rc + xe;
         dst[2] = rn + x;
@@ -609,13 +745,13 @@ __global__ __launch_bounds__(NT) void k_tile(const Job<S>* __restrict__ jobs,
         dst[6] = rn + xw;
         dst[7] = rs + xw;
         dst[8] = rs + xe;
-        A::store(J.pop[par ^ 1], pitch, dst, c, g, f, mfix);
-        R* hn = J.hist[par ^ 1];
-        hn[o] = ph;
-        hn[pitch + o] = ux;
-        hn[2 * pitch + o] = uy;
-        hn[3 * pitch + o] = Sx;
-        hn[4 * pitch + o] = Sy;
+        A::store(J.pop[par ^ 1], pitch, dst, c, gk, fk, mk);
+        R* hw = J.hist[par ^ 1];
+        hw[o] = ph;
+        hw[pitch + o] = ux;
+        hw[2 * pitch + o] = uy;
+        hw[3 * pitch + o] = Sx;
+        hw[4 * pitch + o] = Sy;
     }
 
     if (MODE == MODE_OUT) {
@@ -632,13 +768,16 @@ __global__ __launch_bounds__(NT) void k_tile(const Job<S>* __restrict__ jobs,
             sired[wv] = acc_im;
         }
         __syncthreads();
-        if (threadIdx.x < NPART) {
-            const int k = threadIdx.x;
-            const double s = ((sred[0][k] + sred[1][k]) + (sred[2][k] + sred[3][k]));
-            J.part[(int64_t)(e - J.tile_base) * NPART + k] = s;
+        if (tid < NPART) {
+            double s = 0.0;
+            for (int w = 0; w < NW; ++w) s += sred[w][tid];
+            J.part[(int64_t)(e - J.tile_base) * NPART + tid] = s;
         }
-        if (S::kFix && threadIdx.x == NPART)
-            J.ipart[e - J.tile_base] = (sired[0] + sired[1]) + (sired[2] + sired[3]);
+        if (S::kFix && tid == NPART) {
+            long long s = 0;
+            for (int w = 0; w < NW; ++w) s += sired[w];
+            J.ipart[e - J.tile_base] = s;
+        }
     }
 }
 

@@ -21,7 +21,7 @@ STORAGE = {"fp64": 0, "fp32": 1, "fp16dev": 2, "bf16dev": 3}
 ERRORS = {0: "LBM_OK", -1: "LBM_EINVAL", -2: "LBM_ENOMEM", -3: "LBM_EDEVICE",
           -4: "LBM_ENONFINITE", -5: "LBM_EUNSUPPORTED", -6: "LBM_ESTATE"}
 EXPORTED = [
-    "lbm_default_params", "lbm_workspace_bytes", "lbm_create", "lbm_step", "lbm_set_check",
+    "lbm_default_params", "lbm_workspace_bytes", "lbm_create", "lbm_step", "lbm_set_check", "lbm_check",
     "lbm_read", "lbm_mass", "lbm_energy", "lbm_steps_done", "lbm_state_bytes",
     "lbm_export_state", "lbm_import_state", "lbm_last_step_ms", "lbm_destroy",
     "lbm_batch_workspace_bytes", "lbm_batch_create", "lbm_batch_add", "lbm_batch_remove",
@@ -69,6 +69,7 @@ def lib():
                                           ctypes.POINTER(_VP)]),
             "lbm_step": (ctypes.c_int, [_VP, ctypes.c_int64]),
             "lbm_set_check": (ctypes.c_int, [_VP, ctypes.c_int64]),
+            "lbm_check": (ctypes.c_int, [_VP]),
             "lbm_read": (ctypes.c_int, [_VP, _D, _D, _D, _D]),
             "lbm_mass": (ctypes.c_int, [_VP, _D]),
             "lbm_energy": (ctypes.c_int, [_VP, _D, _D]),
@@ -201,6 +202,15 @@ class Domain:
 
     def set_check(self, every: int):
         _check(lib().lbm_set_check(self._h, int(every)))
+
+    def check(self) -> bool:
+        """True if phi, u and P are finite; False (and the domain refuses further
+        steps) otherwise."""
+        rc = lib().lbm_check(self._h)
+        if rc == -4:
+            return False
+        _check(rc)
+        return True
 
     @property
     def steps(self) -> int:

@@ -297,12 +297,14 @@ class JobSpec:
     steps: int
     arrival_s: float = 0.0
 
-    def workload(self, **kw) -> Workload:
+    def workload(self, mu1: float = 0.3, mu_ratio: float = 50.0, **kw) -> Workload:
         """Drop-on-slab job: L x L periodic, slab rows [0, L/8), drop radius
-        L/4 on the slab, density ratio r with rho2 = 1/r and mu2 = mu1/r."""
+        L/4 on the slab, density ratio r with rho2 = 1/r; viscosities mu1 and
+        mu2 = mu1 / mu_ratio (the stream fixes no viscosity; 0.3 and 50 keep
+        density ratios up to ~200 stable next to solids)."""
         L = self.side
         return droplet_on_slab(nx=L, ny=L, slab_rows=L // 8, R=L / 4.0, theta_deg=self.theta_deg,
-                               rho_ratio=self.rho_ratio, mu_ratio=self.rho_ratio, mu1=0.1,
+                               rho_ratio=self.rho_ratio, mu_ratio=mu_ratio, mu1=mu1,
                                tau_phi=1.0, name=f"job{self.job_id} {L}x{L}", **kw)
 
 
