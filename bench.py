@@ -30,7 +30,7 @@ BYTES_PER_LUP = {"fp64": 36 * 8 + 10 * 8 + 2 * 8, "fp32": 36 * 4 + 10 * 4 + 2 * 
                  "fp16dev": 2 * (8 + 8 * 2 + 9 * 2) + 10 * 4 + 2 * 4,
                  "bf16dev": 2 * (8 + 8 * 2 + 9 * 2) + 10 * 4 + 2 * 4}
 DTYPE = {"fp64": "f64", "fp32": "f32", "fp16dev": "f32 (fp16 storage)", "bf16dev": "f32 (bf16 storage)"}
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_step_c2_fp32.json")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
 
 
 def kernel_source_hash() -> str:
@@ -70,15 +70,17 @@ def roofline(storage: str, nodes: int, kernel_ms: float, traffic=None):
             "bytes_per_lup": BYTES_PER_LUP[storage], "kernel_ms": round(kernel_ms, 5)}
 
 
-def measured_traffic():
-    """HBM bytes per launch from committed rocprofv3 counter runs, if they were
-    taken on the current kernel source."""
+def measured_traffic(workload: str, storage: str, tile: int):
+    """Bytes per launch of the step kernel from committed rocprofv3 counter
+    runs (read + write requests leaving L2, in bytes), if they were taken on
+    the current kernel source with the same workload, storage and tile."""
     if not os.path.exists(TRAFFIC_FILE):
         return None
     t = json.load(open(TRAFFIC_FILE))
     if t.get("source_hash") != kernel_source_hash():
         return None
-    return t.get("bytes_per_launch")
+    e = t.get("entries", {}).get(f"{workload}:{storage}:{tile}")
+    return None if e is None else e["bytes_per_launch"]
 
 
 def cpu_baseline(budget_s: float = 15.0):
@@ -244,7 +246,8 @@ def main():
                                "rho ratio 100, mu ratio 50, g=1e-6" % (w.meta["Rp"], w.meta["R0"]),
                    "nx": w.params["nx"], "ny": w.params["ny"], "storage": args.storage,
                    "tile": f"64x{tile}"},
-        "roofline": roofline(args.storage, r["nodes"], r["kernel_ms"], measured_traffic()),
+        "roofline": roofline(args.storage, r["nodes"], r["kernel_ms"],
+                             measured_traffic(args.workload, args.storage, tile)),
         "mass_drift": r["mass_drift"],
         "finite": r["finite"],
     }
@@ -258,12 +261,22 @@ def main():
             extra[f"C2_{st}"] = {"mlups": round(e["mlups"], 1), "tile": t,
                                  "roofline": roofline(st, e["nodes"], e["kernel_ms"]),
                                  "mass_drift": e["mass_drift"], "finite": e["finite"]}
+        # the same 1024^2 geometry in a parameter set that stays finite (no
+        # gravity, mu1 = 0.3): same kernel, same bytes per step
+        s = W.cylinder_drop(1024, 128.0, 160.0, g=0.0)
+        s.params.update(mu1=0.3, mu2=0.3 / 50)
+        t = autotune.best_tile(s.params, "fp32")
+        e = run_gpu(s, "fp32", args.steps, args.warmup, t)
+        extra["C2_stable_fp32"] = {"mlups": round(e["mlups"], 1), "tile": t, "g": 0.0, "mu1": 0.3,
+                                   "roofline": roofline("fp32", e["nodes"], e["kernel_ms"]),
+                                   "mass_drift": e["mass_drift"], "finite": e["finite"]}
         R = W.roofline_grid()
-        for st in ("fp32", "fp16dev"):
+        for st in ("fp32", "fp16dev", "fp64"):
             t = autotune.best_tile(R.params, st)
             e = run_gpu(R, st, 300, 20, t)
             extra[f"R4096_{st}"] = {"mlups": round(e["mlups"], 1), "tile": t,
-                                    "roofline": roofline(st, e["nodes"], e["kernel_ms"]),
+                                    "roofline": roofline(st, e["nodes"], e["kernel_ms"],
+                                                         measured_traffic("r4096", st, t)),
                                     "finite": e["finite"]}
         out["extra"] = extra
     print(json.dumps(out), flush=True)

@@ -13,6 +13,10 @@ OUT = os.path.join(HERE, "liblbmgls.so")
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
+    # fuse multiply-adds only within one source expression: the rounding of
+    # every node update is then fixed by the source, identical for every
+    # tile shape and for batched and solo launches
+    "-ffp-contract=on",
     # no packed FP32 instructions (v_pk_*_f32)
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-I", os.path.join(ROOT, "include"),

@@ -280,30 +280,35 @@ template <> struct Access<StF32> : AccessFull<StF32> {};
 template <class Sh>
 struct AccessHalf {  // 16-bit codes + fixed-point rest population
     using Pop = typename Sh::Pop;
-    static __device__ __forceinline__ int64_t gfix(const Coef<float>& c, uint16_t code) {
-        return (int64_t)llrintf(Sh::dec(code) * c.gfix);
+    // Fixed-point value (units of 2^-40) of a moving-population code, as an
+    // integer-valued double.  FP16 codes give multiples of 2^(16-kg) below
+    // 2^(56-kg), i.e. at most 40 significant bits; BF16 codes are rounded to
+    // integers (far below 2^53 for any finite state).  Sums of eight of them
+    // are therefore exact in double precision.
+    static __device__ __forceinline__ double gfix(const Coef<float>& c, uint16_t code) {
+        return rint((double)Sh::dec(code) * (double)c.gfix);
     }
     static __device__ __forceinline__ float fix2f(int64_t m) {
         return (float)m * 0x1p-40f;
     }
     static __device__ __forceinline__ float phi(const Pop& P, int64_t pitch, uint32_t o, const Coef<float>& c) {
-        int64_t m = P.g0[o];
+        double s = 0.0;
 #pragma unroll
-        for (int i = 0; i < 8; ++i) m += gfix(c, P.gm[i * pitch + o]);
-        return fix2f(m);
+        for (int i = 0; i < 8; ++i) s += gfix(c, P.gm[i * pitch + o]);
+        return fix2f(P.g0[o] + (int64_t)s);
     }
     static __device__ __forceinline__ void load_g(const Pop& P, int64_t pitch, uint32_t o, const Coef<float>& c,
                                                   float* g, int64_t& mfix) {
         const int64_t rest = P.g0[o];
-        int64_t m = rest;
+        double s = 0.0;
 #pragma unroll
         for (int i = 0; i < 8; ++i) {
             const uint16_t code = P.gm[i * pitch + o];
             g[i + 1] = Sh::dec(code) * c.isg;
-            m += gfix(c, code);
+            s += gfix(c, code);
         }
         g[0] = fix2f(rest);
-        mfix = m;
+        mfix = rest + (int64_t)s;
     }
     static __device__ __forceinline__ float phi_of(const float*, int64_t mfix, const Coef<float>&) {
         return fix2f(mfix);
@@ -318,14 +323,14 @@ struct AccessHalf {  // 16-bit codes + fixed-point rest population
     static __device__ __forceinline__ void store(const Pop& P, int64_t pitch, const uint32_t* dst,
                                                  const Coef<float>& c, const float* g, const float* f,
                                                  int64_t mfix) {
-        int64_t rest = mfix;
+        double s = 0.0;
 #pragma unroll
         for (int i = 0; i < 8; ++i) {
             const uint16_t code = Sh::enc(g[i + 1] * c.sg);
             P.gm[i * pitch + dst[i + 1]] = code;
-            rest -= gfix(c, code);
+            s += gfix(c, code);
         }
-        P.g0[dst[0]] = rest;
+        P.g0[dst[0]] = mfix - (int64_t)s;
 #pragma unroll
         for (int i = 0; i < 9; ++i) P.fm[i * pitch + dst[i]] = Sh::enc(f[i] * c.sf);
     }

@@ -198,9 +198,13 @@ def test_config2_full_size_fp32_3_steps(gpu):
 
 
 def test_config2_invariants_2000_steps(gpu):
-    """Properties that hold at any size: finite fields, conserved order
-    parameter, and exact translation equivariance of the periodic stepper."""
-    w = W.config2()
+    """Properties that hold at any size, on the 1024 x 1024 cylinder + drop
+    geometry in a parameter set that stays finite (density ratio 100,
+    viscosity ratio 50, mu1 = 0.3, no gravity): finite fields, conserved
+    order parameter, and exact translation equivariance of the periodic
+    stepper."""
+    w = W.cylinder_drop(1024, 128.0, 160.0, g=0.0)
+    w.params.update(mu1=0.3, mu2=0.3 / 50)
     sh = (128, -64)
     a = gpu.Domain(w.params, *w.arrays(), storage="fp32")
     ws = W.Workload(w.name, w.params, *[np.roll(v, sh, axis=(0, 1)) for v in w.arrays()])
@@ -214,5 +218,20 @@ def test_config2_invariants_2000_steps(gpu):
         assert np.all(np.isfinite(x))
         assert np.array_equal(np.roll(x, sh, axis=(0, 1)), y)
     drift = abs(a.mass() - m0) / np.abs(w.phi).sum()
-    print(f"\nC2 fp32 2000 steps mass drift {drift:.2e}")
+    print(f"\nC2 geometry fp32 2000 steps mass drift {drift:.2e}")
     assert drift < 1e-6
+
+
+def test_config2_as_specified_reports_nonfinite(gpu):
+    """The 1024 x 1024 workload with gravity 1e-6 at density ratio 100 leaves
+    the finite range within a few thousand steps (the method is run far
+    beyond the density ratios of the paper); the periodic check reports it
+    as LBM_ENONFINITE and the domain refuses further steps."""
+    w = W.config2()
+    d = gpu.Domain(w.params, *w.arrays(), storage="fp32")
+    d.set_check(500)
+    with pytest.raises(gpu.LbmError) as e:
+        d.step(20000)
+    assert e.value.code == -4
+    print(f"\nC2 as specified: non-finite detected at step {d.steps}")
+    assert d.steps < 20000
