@@ -139,6 +139,18 @@ def serve_bench(args):
     jobs = W.job_stream(n_jobs=args.jobs, seed=4, ratio_range=(lo, hi), rate_per_s=rate)
     ref_ids = {j.job_id for j in jobs[:: args.ref_every]}
     refs = {}
+    t_start = time.perf_counter()
+
+    def progress(tag):
+        count = [0]
+
+        def cb(res):
+            count[0] += 1
+            if count[0] % 16 == 0 or count[0] == len(jobs):
+                print(f"[serve] {tag}: {count[0]}/{len(jobs)} jobs retired, "
+                      f"{time.perf_counter() - t_start:.0f} s", file=sys.stderr, flush=True)
+        return cb
+
     for j in jobs:
         if j.job_id in ref_ids:
             w = j.workload()
@@ -150,19 +162,34 @@ def serve_bench(args):
             except lbmgls.LbmError:
                 pass
             r.close()
+    print(f"[serve] {len(refs)} FP64 references done, {time.perf_counter() - t_start:.0f} s",
+          file=sys.stderr, flush=True)
     modes = []
     runs = [("solo", "fp32")] + [("batched", s) for s in ("fp32", "fp16dev", "bf16dev")]
     for kind, st in runs:
         if kind == "solo":
-            stats = serve.run_solo(jobs, storage=st, tile=8, keep_phi=True)
+            stats = serve.run_solo(jobs, storage=st, tile=8, keep_phi=True,
+                                   on_retire=progress(f"{kind}-{st}"))
         else:
             srv = serve.Server(storage=st, budget_bytes=args.budget_gib << 30, tick_steps=args.tick,
-                               tile=8, keep_phi=True)
+                               tile=8, keep_phi=True, on_retire=progress(f"{kind}-{st}"))
             stats = srv.run(jobs)
             srv.close()
         s = stats.summary()
         errs = [float(np.linalg.norm(j.phi - refs[j.job_id]) / np.linalg.norm(refs[j.job_id]))
                 for j in stats.jobs if j.status == "done" and j.job_id in refs and j.phi is not None]
+        if args.jobs_out:
+            spec = {j.job_id: j for j in jobs}
+            with open(args.jobs_out, "a") as fh:
+                for j in stats.jobs:
+                    js = spec[j.job_id]
+                    err = (float(np.linalg.norm(j.phi - refs[j.job_id]) / np.linalg.norm(refs[j.job_id]))
+                           if j.status == "done" and j.job_id in refs and j.phi is not None else None)
+                    fh.write(json.dumps({"mode": s["mode"], "job": j.job_id, "side": js.side,
+                                         "theta": round(js.theta_deg, 2), "ratio": round(js.rho_ratio, 2),
+                                         "steps": js.steps, "status": j.status,
+                                         "drift": None if not np.isfinite(j.mass_drift) else j.mass_drift,
+                                         "phi_err": err, "latency": round(j.latency, 4)}) + "\n")
         s["max_rel_phi_err_vs_fp64"] = max(errs) if errs else None
         s["phi_err_jobs"] = len(errs)
         modes.append(s)
@@ -206,6 +233,7 @@ def main():
     ap.add_argument("--budget-gib", type=int, default=4)
     ap.add_argument("--tick", type=int, default=500)
     ap.add_argument("--ref-every", type=int, default=8)
+    ap.add_argument("--jobs-out", default="", help="append one JSON record per job and mode")
     args = ap.parse_args()
 
     if args.gpus != 1:

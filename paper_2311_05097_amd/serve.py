@@ -82,13 +82,14 @@ class Server:
 
     def __init__(self, storage: str = "fp32", budget_bytes: int = 4 << 30, tick_steps: int = 500,
                  max_members: int = 128, tile: int = 8, keep_phi: bool = False,
-                 job_overrides: dict | None = None):
+                 job_overrides: dict | None = None, on_retire=None):
         self.storage = storage
         self.budget = int(budget_bytes)
         self.tick = int(tick_steps)
         self.tile = int(tile)
         self.keep_phi = keep_phi
         self.overrides = dict(job_overrides or {})
+        self.on_retire = on_retire
         self.batch = lbmgls.Batch(storage=storage, tile=tile, max_members=max_members,
                                   max_tiles=max_members * (1024 * 1024 // (64 * 4)))
         self.resident: list = []  # (JobResult, Domain, remaining, denominator, mass0)
@@ -117,6 +118,8 @@ class Server:
         self.batch.remove(d)
         d.close()
         self.used -= entry[5]
+        if self.on_retire is not None:
+            self.on_retire(res)
 
     def run(self, jobs: list[JobSpec], realtime: bool = True) -> ServeStats:
         pending = sorted(jobs, key=lambda j: (j.arrival_s, j.job_id))
@@ -167,7 +170,8 @@ class Server:
 
 
 def run_solo(jobs: list[JobSpec], storage: str = "fp32", tile: int = 0, check_every: int = 1000,
-             realtime: bool = True, keep_phi: bool = False, job_overrides: dict | None = None) -> ServeStats:
+             realtime: bool = True, keep_phi: bool = False, job_overrides: dict | None = None,
+             on_retire=None) -> ServeStats:
     """The plain per-job path: one job at a time, FIFO, per-step launches."""
     overrides = dict(job_overrides or {})
     pending = sorted(jobs, key=lambda j: (j.arrival_s, j.job_id))
@@ -197,4 +201,6 @@ def run_solo(jobs: list[JobSpec], storage: str = "fp32", tile: int = 0, check_ev
         res.finished = time.perf_counter() - t0
         d.close()
         out.append(res)
+        if on_retire is not None:
+            on_retire(res)
     return ServeStats(f"solo-{storage}", out, time.perf_counter() - t0)
