@@ -78,12 +78,20 @@ struct StF64 {
     using R = double;
     struct Pop { double* p; };  // [18][pitch]: g_0..g_8, f_0..f_8
     static constexpr bool kFix = false;
+    static constexpr bool kRel = false;
     static constexpr int kMode = 0;
 };
 struct StF32 {
     using R = float;
     struct Pop { float* p; };
     static constexpr bool kFix = false;
+    // g_0 is stored relative to the order parameter that the same step writes
+    // to history plane 0 at the same node: the stored value is g_0 - phi^n, of
+    // the size of the moving populations.  An O(1) rest population rounded to
+    // FP32 every step carries a rounding bias that is the same at every bulk
+    // node (same state, same rounding direction), so the total order parameter
+    // drifts linearly in time; the relative form rounds only the small part.
+    static constexpr bool kRel = true;
     static constexpr int kMode = 1;
 };
 struct StHalfBase {
@@ -91,6 +99,7 @@ struct StHalfBase {
     // g_0 as 64-bit fixed point, g_1..g_8 and f_0..f_8 as 16-bit codes
     struct Pop { int64_t* g0; uint16_t* gm; uint16_t* fm; };
     static constexpr bool kFix = true;
+    static constexpr bool kRel = false;
 };
 
 __device__ __forceinline__ uint16_t f16_enc(float v) {
@@ -430,9 +439,9 @@ __global__ __launch_bounds__(TileCfg<TY>::NT) void k_tile(const Job<S>* __restri
             A::load_f(cur, pitch, o, c, f[kk]);
 #pragma unroll
             for (int v = 0; v < 5; ++v) hp[kk][v] = hprev[v * pitch + o];
-            *sp = A::phi_of(g[kk], mfix[kk], c);
+            *sp = S::kRel ? hp[kk][0] + A::phi_of(g[kk], mfix[kk], c) : A::phi_of(g[kk], mfix[kk], c);
         } else {
-            *sp = A::phi(cur, pitch, o, c);
+            *sp = S::kRel ? hprev[o] + A::phi(cur, pitch, o, c) : A::phi(cur, pitch, o, c);
         }
         zz[k] = st[o];
     }
@@ -451,6 +460,8 @@ __global__ __launch_bounds__(TileCfg<TY>::NT) void k_tile(const Job<S>* __restri
         const uint32_t o = (uint32_t)(s_row[ly] + s_col[lx]);
         if (MODE == MODE_INIT)
             sphi[ly * W3 + lx] = (R)J.in[o];
+        else if (S::kRel)
+            sphi[ly * W3 + lx] = hprev[o] + A::phi(cur, pitch, o, c);
         else
             sphi[ly * W3 + lx] = A::phi(cur, pitch, o, c);
     }
@@ -579,7 +590,7 @@ __global__ __launch_bounds__(TileCfg<TY>::NT) void k_tile(const Job<S>* __restri
             const R emu = c.eta * mu, ia = R(1) / c.a;
             const R jxa = ph * ux * ia, jya = ph * uy * ia;
             R m[9], gg[9], ff[9];
-            gg[0] = ph + (c.w0 - R(1)) * emu;
+            gg[0] = S::kRel ? (c.w0 - R(1)) * emu : ph + (c.w0 - R(1)) * emu;
             gg[1] = c.w1 * (emu + jxa);
             gg[3] = c.w1 * (emu - jxa);
             gg[2] = c.w1 * (emu + jya);
@@ -671,7 +682,9 @@ __global__ __launch_bounds__(TileCfg<TY>::NT) void k_tile(const Job<S>* __restri
                        + c.k9s_2D * z * z * ph * ph + c.k3s_D * psi0 * ph * (ph * ph + z * z - R(1))
                        + R(2) * c.k3Ds_16 * (qx * dpx + qy * dpy);
             const R ek = R(0.5) * rho * (ux * ux + uy * uy);
-            acc_m += (double)ph;
+            // relative rest population: sum the history value and the small
+            // remainder separately, so the readout adds no FP32 rounding
+            acc_m += S::kRel ? (double)php + (double)A::phi_of(gk, mk, c) : (double)ph;
             acc_ef += (double)ef;
             acc_ek += (double)ek;
             if (S::kFix) acc_im += (long long)mk;
@@ -750,6 +763,9 @@ __global__ __launch_bounds__(TileCfg<TY>::NT) void k_tile(const Job<S>* __restri
         dst[6] = rn + xw;
         dst[7] = rs + xw;
         dst[8] = rs + xe;
+        // relative rest population: g_0 - phi^n with phi^n the value written
+        // to history below; (php - ph) is exact for nearby values
+        if (S::kRel) gk[0] += php - ph;
         A::store(J.pop[par ^ 1], pitch, dst, c, gk, fk, mk);
         R* hw = J.hist[par ^ 1];
         hw[o] = ph;

@@ -60,6 +60,11 @@ def lib():
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"{LIB_PATH} is not built; run __graft_entry__.build() first")
+        if DEVICE == "cuda":
+            # torch brings its own HIP runtime; load it first so that the
+            # library binds to the same runtime (and device context) as the
+            # tensors and streams it is handed
+            _torch()
         L = ctypes.CDLL(LIB_PATH)
         P = ctypes.POINTER(LbmParams)
         sig = {

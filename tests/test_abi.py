@@ -5,6 +5,7 @@ import ctypes
 import os
 import re
 import subprocess
+import sys
 
 import pytest
 
@@ -70,3 +71,18 @@ def test_workspace_size_and_validation_host_only():
         lbmgls.workspace_bytes(dict(w.params, nx=4), "fp32")
     with pytest.raises(lbmgls.LbmError):
         lbmgls.workspace_bytes(dict(w.params, d0=1.2), "fp32")
+
+
+def test_binding_shares_torchs_hip_runtime():
+    """Loading the library through the binding must not bring a second HIP
+    runtime into the process: torch ships its own, and a library bound to a
+    different runtime cannot use torch's streams, events or device context."""
+    code = (
+        "import sys; sys.path.insert(0, %r)\n"
+        "from paper_2311_05097_amd import lbmgls\n"
+        "lbmgls.lib()\n"
+        "maps = {l.split()[-1] for l in open('/proc/self/maps') if 'libamdhip64' in l}\n"
+        "print(len(maps))\n" % ROOT)
+    out = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=300)
+    assert out.returncode == 0, out.stderr
+    assert out.stdout.strip().splitlines()[-1] == "1"

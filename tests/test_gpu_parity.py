@@ -1,7 +1,7 @@
 """GPU (HIP, gfx950) versus the FP64 CPU oracle, element by element.
 
 Bars: FP64 storage/arithmetic <= 1e-12 relative (2-norm over the field) on
-phi, u and P; FP32 <= 1e-5 relative on phi and P; the 16-bit deviation
+phi, u and P; FP32 <= 1e-5 relative on phi, u and P; the 16-bit deviation
 storage modes are measured against the oracle with the tolerances derived
 from their quantisation (see the per-test comments).  Mass drift is printed
 for every run.
@@ -61,11 +61,29 @@ def test_config1_fp64_1000_steps(gpu):
 def test_config1_fp32_1000_steps(gpu):
     w = W.config1()
     d, o, errs, drift = _pair(gpu, w, "fp32", 1000)
-    assert errs["phi"][0] <= 1e-5 and errs["P"][0] <= 1e-5
-    # u is a spurious-current-sized field (|u| ~ 1e-4) obtained from a sum of
-    # O(1e-4) populations: FP32 keeps ~1e-3 of it
-    assert errs["ux"][0] <= 1e-3 and errs["uy"][0] <= 1e-3
-    assert drift <= 1e-6
+    # the FP32 bar: 1e-5 relative on phi, u and P after 1000 steps
+    for k, (e2, emax) in errs.items():
+        assert e2 <= 1e-5, (k, e2)
+    # the rest population is stored relative to the node's order parameter,
+    # so only small values are rounded: the total drifts by round-off only
+    assert drift <= 1e-10
+
+
+@pytest.mark.parametrize("storage,tol", [("fp64", 1e-12), ("fp32", 1e-10), ("fp16dev", 0.0), ("bf16dev", 0.0)])
+def test_long_run_mass_drift(gpu, storage, tol):
+    """Sum of phi over 15 000 steps of a 128^2 drop on a slab (density ratio
+    100, 57 degrees): the collision conserves it exactly, so what remains is
+    the rounding of the stored populations.  A rest population rounded to FP32
+    every step drifts by ~3e-4 here; the relative FP32 form and the 16-bit
+    modes' fixed-point form do not."""
+    w = W.JobSpec(52, 128, 56.87, 99.04, 15000).workload()
+    d = gpu.Domain(w.params, *w.arrays(), storage=storage)
+    m0 = d.mass()
+    d.set_check(5000)
+    d.step(15000)
+    drift = abs(d.mass() - m0) / np.abs(w.phi).sum()
+    print(f"\n{storage}: mass drift after 15000 steps {drift:.3e}")
+    assert drift <= tol
 
 
 @pytest.mark.parametrize("storage,tol_phi,tol_u", [("fp64", 1e-12, 1e-12), ("fp32", 1e-5, 1e-3),
@@ -128,7 +146,7 @@ def test_batch_equals_solo_bitwise(gpu):
     ws = [W.random_state(nx, ny, seed=s, rho2=0.2, mu2=0.03) for nx, ny, s in
           ((128, 64, 1), (70, 90, 2), (256, 256, 3))]
     budgets = [40, 25, 33]
-    for storage in ("fp32", "fp16dev"):
+    for storage in ("fp64", "fp32", "fp16dev", "bf16dev"):
         solo = []
         for w, nb in zip(ws, budgets):
             d = gpu.Domain(w.params, *w.arrays(), storage=storage)
