@@ -62,12 +62,38 @@ def run_gpu(workload, storage: str, steps: int, warmup: int, tile: int = 0):
                 mlups=n * steps / dt / 1e6, kernel_ms=kernel_ms, mass_drift=drift, finite=finite)
 
 
-def roofline(storage: str, nodes: int, kernel_ms: float, traffic=None):
+def copy_ceiling(nbytes_moved: int, reps: int = 20) -> float:
+    """GB/s (read + written) of torch's device-to-device copy moving the same
+    number of bytes as one step (half read, half written): the bandwidth a
+    plain streaming kernel reaches on this device at this size."""
+    import torch
+    n = max(1024, nbytes_moved // 8 // 64 * 64)  # float32 elements per buffer
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    e1.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del a, b
+    return 2 * n * 4 / (ms * 1e-3) / 1e9
+
+
+def roofline(storage: str, nodes: int, kernel_ms: float, traffic=None, copy_gbs=None):
     b = BYTES_PER_LUP[storage] * nodes
     achieved = b / (kernel_ms * 1e-3) / 1e9
-    return {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
-            "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": traffic,
-            "bytes_per_lup": BYTES_PER_LUP[storage], "kernel_ms": round(kernel_ms, 5)}
+    out = {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+           "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": traffic,
+           "bytes_per_lup": BYTES_PER_LUP[storage], "kernel_ms": round(kernel_ms, 5)}
+    if copy_gbs:
+        out["copy_GBps"] = round(copy_gbs, 1)
+        out["frac_of_copy"] = round(achieved / copy_gbs, 4)
+    return out
 
 
 def measured_traffic(workload: str, storage: str, tile: int):
@@ -255,6 +281,13 @@ def main():
     from paper_2311_05097_amd import workloads as W
     from paper_2311_05097_amd import autotune
     w = W.config2() if args.workload == "c2" else W.roofline_grid()
+    R = W.roofline_grid()
+    nw, nr = w.params["nx"] * w.params["ny"], R.params["nx"] * R.params["ny"]
+    # copy ceilings first, in a fresh allocator state
+    ceil = {("w", args.storage): copy_ceiling(BYTES_PER_LUP[args.storage] * nw)}
+    if not args.no_extra:
+        for st in ("fp32", "fp16dev", "fp64"):
+            ceil[("r", st)] = copy_ceiling(BYTES_PER_LUP[st] * nr)
     tile = args.tile or autotune.best_tile(w.params, args.storage)
     r = run_gpu(w, args.storage, args.steps, args.warmup, tile)
     out = {
@@ -275,7 +308,8 @@ def main():
                    "nx": w.params["nx"], "ny": w.params["ny"], "storage": args.storage,
                    "tile": f"64x{tile}"},
         "roofline": roofline(args.storage, r["nodes"], r["kernel_ms"],
-                             measured_traffic(args.workload, args.storage, tile)),
+                             measured_traffic(args.workload, args.storage, tile),
+                             ceil[("w", args.storage)]),
         "mass_drift": r["mass_drift"],
         "finite": r["finite"],
     }
@@ -298,13 +332,13 @@ def main():
         extra["C2_stable_fp32"] = {"mlups": round(e["mlups"], 1), "tile": t, "g": 0.0, "mu1": 0.3,
                                    "roofline": roofline("fp32", e["nodes"], e["kernel_ms"]),
                                    "mass_drift": e["mass_drift"], "finite": e["finite"]}
-        R = W.roofline_grid()
         for st in ("fp32", "fp16dev", "fp64"):
             t = autotune.best_tile(R.params, st)
             e = run_gpu(R, st, 300, 20, t)
             extra[f"R4096_{st}"] = {"mlups": round(e["mlups"], 1), "tile": t,
                                     "roofline": roofline(st, e["nodes"], e["kernel_ms"],
-                                                         measured_traffic("r4096", st, t)),
+                                                         measured_traffic("r4096", st, t),
+                                                         ceil[("r", st)]),
                                     "finite": e["finite"]}
         out["extra"] = extra
     print(json.dumps(out), flush=True)
