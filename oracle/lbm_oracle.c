@@ -19,7 +19,12 @@
  *   - finite differences: second-order isotropic central schemes (Sec. 3.2,
  *     last paragraph);
  *   - macroscopic recovery u*, f, u, P (Sec. 3.2, Eqs. uStar and u);
- *   - procedure steps 1-6 and 11 of Sec. 3.3 (stationary solids).
+ *   - procedure steps 1-6 and 11 of Sec. 3.3, and with free rigid particles
+ *     steps 7-10: hydrodynamic force and torque (Eq. Ff), the particle
+ *     equations of Sec. 2.4 by explicit Euler, the tanh indicator of every
+ *     particle regenerated at its new position, the internal-fluid
+ *     corrections (Eq. Ffin), the force mu_phi0 grad phi0 (Eq. muPhi0) and the
+ *     short-range repulsion of Sec. 4.5.
  *
  * Readings where the paper is silent or ambiguous (each one is listed in the
  * design notes of the repository):
@@ -43,8 +48,31 @@
  *   R-CLAMP  the density and viscosity laws (Eq. rho) are evaluated on phi
  *            clamped to [-1, 1] (overshoots past -1 would make rho <= 0 at
  *            density ratios >= 100); grad rho is the gradient of that field.
- *   Stationary solids only: u_s = 0 and the mu_phi0 grad phi0 force, which
- *   the paper adds only for freely moving solids, is absent.
+ *   R-STAT   stationary solids: u_s = 0 and no mu_phi0 grad phi0 force (the
+ *            paper adds it only for freely moving solids).
+ *   R-PART   free particles (Sec. 2.4, procedure steps 7-10):
+ *            - phi0 = clamp(phi0_static + sum_k phi0_k, 0, 1), phi0_k the
+ *              tanh indicator of Sec. 4.5 with the periodic nearest image,
+ *              set to 0 beyond |x - x_k| >= R_k + 5 D (where it is < 3e-9);
+ *            - each node has one owner: the largest of phi0_static and the
+ *              phi0_k (ties to the static solid, then the lower k); cos(theta)
+ *              and u_s = u_p + omega_p x (x - x_p) are the owner's (u_s = 0
+ *              for the static solid), and mu_phi0 grad phi0 is added where
+ *              the owner is a particle;
+ *            - F_f, T_f sum -rho f over the nodes the particle owns; rho in
+ *              (1 - rho/rho_p), F^in = rho V_p du_p/dt and I_f = I_p rho/rho_p
+ *              is the indicator-weighted mean density of those nodes;
+ *            - M_p = rho_p pi R^2, I_p = M_p R^2 / 2, V_p = pi R^2 (disks);
+ *            - explicit Euler over one step, all right-hand sides at the old
+ *              level; F^in, T^in are the explicit differences of that update
+ *              and enter the next one;
+ *            - the particles move after each macroscopic update of the loop,
+ *              not after the initial one (procedure: step 1, then steps 2-10
+ *              repeated); the next update of the fields sees the new phi0.
+ *            - repulsion (Sec. 4.5) as printed, particle-particle with the
+ *              nearest periodic image, particle-wall against optional
+ *              axis-aligned wall planes (mirror image of the particle);
+ *              none when the stiffness parameter is <= 0.
  *   Periodic in x and y.
  */
 #include <math.h>
@@ -66,7 +94,17 @@ typedef struct {
     double gx, gy, rho_ref;      /* R-FB                                    */
     double fbx, fby;             /* R-FB                                    */
     double solid_eps;            /* R-NU                                    */
+    double rep_xi, rep_eps;      /* repulsion threshold and stiffness (Sec. 4.5) */
+    double wall_x0, wall_x1, wall_y0, wall_y1; /* wall planes for the repulsion  */
+    int32_t walls;               /* bit 0: y0, 1: y1, 2: x0, 3: x1 present  */
 } orc_params;
+
+/* One free rigid disk (Sec. 2.4): centre, translational and angular velocity,
+ * radius, density, cos of the contact angle of phase 1 on its surface. */
+enum { P_X, P_Y, P_UX, P_UY, P_OM, P_R, P_RHO, P_COS, NPIN };
+/* Per-particle outputs: hydrodynamic force and torque of the last update,
+ * internal-fluid corrections carried to the next one, internal density. */
+enum { Q_FX, Q_FY, Q_T, Q_FINX, Q_FINY, Q_TIN, Q_RHOIN, NPOUT };
 
 /* ---- D2Q9 lattice: velocity order as in rows 2-3 of M_0 (Sec. 4) ---- */
 static const int CX[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
@@ -317,8 +355,11 @@ enum {
     F_S2A, F_S2B, F_H,
     /* history of the previous time level */
     F_PHIUXP, F_PHIUYP, F_TXXP, F_TXYP, F_TYYP, F_QP, F_ULX, F_ULY,
-    /* static */
+    /* static (regenerated from the particles every step) */
     F_PHI0, F_PSI,
+    /* stationary solid as given, node owner (-1 static, k particle), solid
+     * velocity, mu_phi0 (Eq. muPhi0) */
+    F_ZB, F_CB, F_OWN, F_USOLX, F_USOLY, F_MUZ,
     NFIELDS
 };
 static const char *FIELD_NAMES[NFIELDS] = {
@@ -326,7 +367,8 @@ static const char *FIELD_NAMES[NFIELDS] = {
     "Fcx", "Fcy", "Fx", "Fy", "ustarx", "ustary", "asx", "asy", "ux", "uy", "P",
     "s2a", "s2b", "H",
     "phiux_p", "phiuy_p", "Txx_p", "Txy_p", "Tyy_p", "q_p", "ulagx", "ulagy",
-    "phi0", "psi"};
+    "phi0", "psi",
+    "phi0_static", "cos_static", "owner", "usolx", "usoly", "mu_phi0"};
 
 typedef struct orc_state {
     orc_params p;
@@ -336,6 +378,9 @@ typedef struct orc_state {
     double *g, *f, *gpost, *fpost; /* [9][N] each */
     double *fld[NFIELDS];
     long steps;
+    int np;          /* number of free particles               */
+    double *pin;     /* [np][NPIN]  particle state             */
+    double *pout;    /* [np][NPOUT] forces and corrections     */
 } orc_state;
 
 static double clamp01(double v) { return v < 0.0 ? 0.0 : (v > 1.0 ? 1.0 : v); }
@@ -360,11 +405,12 @@ static void viscous_rates(const orc_params *p, double rho, double muv, double ph
 /* Steps 5-6 at one node (Sec. 3.2, Eqs. uStar and u).  f: the 9 flow
  * distributions; F: total force; S: mass flux; drho: grad rho; q_p: the
  * history value of rho u.u - S.u; (u0x, u0y): the given velocity, used only
- * when init != 0 (R-INIT).  out = u*x, u*y, f_x dt, f_y dt, ux, uy, s2a, s2b,
- * H, P. */
+ * when init != 0 (R-INIT); (usolx, usoly): the solid velocity u_s at the node.
+ * out = u*x, u*y, f_x dt, f_y dt, ux, uy, s2a, s2b, H, P. */
 void orc_macro_node(const orc_params *p, int init, const double f[9], double rho, double muv,
                     double phi0, double Fx, double Fy, double Sx, double Sy, double drx,
-                    double dry, double q_p, double u0x, double u0y, double out[10])
+                    double dry, double q_p, double u0x, double u0y, double usolx, double usoly,
+                    double out[10])
 {
     const double d0 = p->d0, c2 = 1.0, cs2 = d0, K = 1.0 - d0;
     double w[9];
@@ -382,8 +428,8 @@ void orc_macro_node(const orc_params *p, int init, const double f[9], double rho
         usx = jx / rho + Fx / (2.0 * rho); /* Eq. uStar, dt = 1 */
         usy = jy / rho + Fy / (2.0 * rho);
     }
-    /* stationary solid: u_s = 0; f = phi0 (u_s - u*) / dt */
-    double ax = phi0 * (0.0 - usx), ay = phi0 * (0.0 - usy);
+    /* f = phi0 (u_s - u*) / dt; u_s = 0 for a stationary solid */
+    double ax = phi0 * (usolx - usx), ay = phi0 * (usoly - usy);
     double ux = init ? usx : usx + ax / 2.0; /* Eq. u */
     double uy = init ? usy : usy + ay / 2.0;
     double s2a, s2b, H;
@@ -446,21 +492,36 @@ static void macro(orc_state *st, int init)
         orc_grad(nx, ny, T[1][b], dTx, dTy);
         for (long o = 0; o < N; ++o) out[o] += dTy[o]; /* d_y T_y,beta */
     }
-    /* total force F = mu grad(phi) + F_b + F_c */
+    /* mu_phi0 (Eq. muPhi0) where a free particle owns the node (R-PART) */
+    double *gzx = malloc(N * sizeof(double)), *gzy = malloc(N * sizeof(double));
+    double *lphi = malloc(N * sizeof(double));
+    orc_grad(nx, ny, F[F_PHI0], gzx, gzy);
+    orc_lap(nx, ny, F[F_PHI], lphi);
+    for (long o = 0; o < N; ++o) {
+        F[F_MUZ][o] = 0.0;
+        int k = (int)F[F_OWN][o];
+        if (k < 0) continue;
+        double f = F[F_PHI][o], z = F[F_PHI0][o], c = st->pin[k * NPIN + P_COS];
+        const double sg = p->sigma, D = p->D;
+        F[F_MUZ][o] = 9.0 * sg / D * z * f * f + 3.0 * sg * c / D * f * (3.0 * z * z + f * f - 1.0)
+                    - 3.0 * D * sg * c / 8.0 * lphi[o];
+    }
+    /* total force F = mu grad(phi) + mu_phi0 grad(phi0) + F_b + F_c */
     for (long o = 0; o < N; ++o) {
         double mu = F[F_MU][o], rho = F[F_RHO][o], z = F[F_PHI0][o];
         double fbx = (rho - p->rho_ref) * p->gx + (1.0 - z) * p->fbx;
         double fby = (rho - p->rho_ref) * p->gy + (1.0 - z) * p->fby;
-        F[F_FX][o] = mu * F[F_DPHIX][o] + fbx + F[F_FCX][o];
-        F[F_FY][o] = mu * F[F_DPHIY][o] + fby + F[F_FCY][o];
+        F[F_FX][o] = mu * F[F_DPHIX][o] + F[F_MUZ][o] * gzx[o] + fbx + F[F_FCX][o];
+        F[F_FY][o] = mu * F[F_DPHIY][o] + F[F_MUZ][o] * gzy[o] + fby + F[F_FCY][o];
     }
+    free(gzx); free(gzy); free(lphi);
     /* steps 5-6 */
     for (long o = 0; o < N; ++o) {
         double fi[9], out[10];
         for (int i = 0; i < 9; ++i) fi[i] = st->f[i * N + o];
         orc_macro_node(p, init, fi, F[F_RHO][o], F[F_MUV][o], F[F_PHI0][o], F[F_FX][o], F[F_FY][o],
                        F[F_SX][o], F[F_SY][o], F[F_DRHOX][o], F[F_DRHOY][o], F[F_QP][o],
-                       F[F_ULX][o], F[F_ULY][o], out);
+                       F[F_ULX][o], F[F_ULY][o], F[F_USOLX][o], F[F_USOLY][o], out);
         F[F_USX][o] = out[0]; F[F_USY][o] = out[1];
         F[F_AX][o] = out[2];  F[F_AY][o] = out[3];
         F[F_UX][o] = out[4];  F[F_UY][o] = out[5];
@@ -490,18 +551,156 @@ static void save_history(orc_state *st)
     }
 }
 
+static const double PI = 3.14159265358979323846;
+
+/* Nearest periodic image of a coordinate difference. */
+static double per(double d, int n)
+{
+    return d - n * floor(d / n + 0.5);
+}
+
+/* Procedure step 9 (and step 1): the indicator field from the stationary
+ * solid and the particles at their current positions, the node owners, the
+ * owner's contact angle (psi = cos(theta) phi0) and solid velocity (R-PART). */
+static void particle_statics(orc_state *st)
+{
+    const orc_params *p = &st->p;
+    const int nx = p->nx, ny = p->ny;
+    double **F = st->fld;
+    for (int y = 0; y < ny; ++y)
+        for (int x = 0; x < nx; ++x) {
+            long o = (long)y * nx + x;
+            double best = F[F_ZB][o], sum = F[F_ZB][o], c = F[F_CB][o];
+            int own = -1;
+            for (int k = 0; k < st->np; ++k) {
+                const double *q = st->pin + k * NPIN;
+                double r = hypot(per(x - q[P_X], nx), per(y - q[P_Y], ny));
+                double zk = r < q[P_R] + 5.0 * p->D ? 0.5 + 0.5 * tanh((q[P_R] - r) / (p->D / 2.0)) : 0.0;
+                sum += zk;
+                if (zk > best) { best = zk; own = k; c = q[P_COS]; }
+            }
+            double z = clamp01(sum);
+            F[F_PHI0][o] = z;
+            F[F_PSI][o] = c * z;
+            F[F_OWN][o] = own;
+            F[F_USOLX][o] = 0.0;
+            F[F_USOLY][o] = 0.0;
+            if (own >= 0) { /* u_s = u_p + omega_p x (x - x_p) */
+                const double *q = st->pin + own * NPIN;
+                double rx = per(x - q[P_X], nx), ry = per(y - q[P_Y], ny);
+                F[F_USOLX][o] = q[P_UX] - q[P_OM] * ry;
+                F[F_USOLY][o] = q[P_UY] + q[P_OM] * rx;
+            }
+        }
+}
+
+/* Sec. 4.5: the repulsion on particle k from particle j (pp) or from the
+ * mirror image x' of k across a wall (pw: stiffness eps/2, radii 2R). */
+static void repulsion(double dx, double dy, double Rsum, double xi, double eps, double out[2])
+{
+    double d = hypot(dx, dy), m;
+    if (d > Rsum + xi) m = 0.0;
+    else if (d >= Rsum) m = (Rsum + xi - d) * (Rsum + xi - d) / eps;
+    else m = (Rsum - d) / eps;
+    out[0] = m * dx;
+    out[1] = m * dy;
+}
+
+void orc_repulsion(double dx, double dy, double Rsum, double xi, double eps, double out[2])
+{
+    repulsion(dx, dy, Rsum, xi, eps, out);
+}
+
+/* Procedure steps 7, 8 and 10 after a macroscopic update (R-PART). */
+static void particles_update(orc_state *st)
+{
+    const orc_params *p = &st->p;
+    const int nx = p->nx, ny = p->ny, np = st->np;
+    const long N = st->N;
+    double **F = st->fld;
+    double *acc = calloc((size_t)np * 5, sizeof(double)); /* Fx, Fy, T, sum phi0 rho, sum phi0 */
+    for (int y = 0; y < ny; ++y)
+        for (int x = 0; x < nx; ++x) {
+            long o = (long)y * nx + x;
+            int k = (int)F[F_OWN][o];
+            if (k < 0) continue;
+            const double *q = st->pin + k * NPIN;
+            double rho = F[F_RHO][o];
+            double fx = rho * F[F_AX][o], fy = rho * F[F_AY][o]; /* rho f dt, Eq. Ff */
+            double rx = per(x - q[P_X], nx), ry = per(y - q[P_Y], ny);
+            acc[k * 5 + 0] -= fx;
+            acc[k * 5 + 1] -= fy;
+            acc[k * 5 + 2] -= rx * fy - ry * fx;
+            acc[k * 5 + 3] += F[F_PHI0][o] * rho;
+            acc[k * 5 + 4] += F[F_PHI0][o];
+        }
+    (void)N;
+    double *nw = malloc((size_t)np * NPIN * sizeof(double));
+    for (int k = 0; k < np; ++k) {
+        const double *q = st->pin + k * NPIN;
+        double *o = st->pout + k * NPOUT;
+        const double R = q[P_R], rp = q[P_RHO];
+        const double V = PI * R * R, Mp = rp * V, Ip = Mp * R * R / 2.0;
+        double rin = acc[k * 5 + 4] > 0.0 ? acc[k * 5 + 3] / acc[k * 5 + 4] : 0.0;
+        o[Q_FX] = acc[k * 5 + 0];
+        o[Q_FY] = acc[k * 5 + 1];
+        o[Q_T] = acc[k * 5 + 2];
+        o[Q_RHOIN] = rin;
+        double fr[2] = {0.0, 0.0}, t[2];
+        for (int j = 0; j < np && p->rep_eps > 0.0; ++j) {
+            if (j == k) continue;
+            const double *qj = st->pin + j * NPIN;
+            repulsion(per(q[P_X] - qj[P_X], nx), per(q[P_Y] - qj[P_Y], ny), R + qj[P_R], p->rep_xi, p->rep_eps, t);
+            fr[0] += t[0]; fr[1] += t[1];
+        }
+        const double wall[4] = {p->wall_y0, p->wall_y1, p->wall_x0, p->wall_x1};
+        for (int w = 0; w < 4 && p->rep_eps > 0.0; ++w) {
+            if (!(p->walls >> w & 1)) continue;
+            double dx = 0.0, dy = 0.0; /* x_p - x', x' the mirror image of x_p */
+            if (w < 2) dy = 2.0 * (q[P_Y] - wall[w]);
+            else dx = 2.0 * (q[P_X] - wall[w]);
+            repulsion(dx, dy, 2.0 * R, p->rep_xi, p->rep_eps / 2.0, t);
+            fr[0] += t[0]; fr[1] += t[1];
+        }
+        /* Eq. (particle), explicit Euler with dt = 1 */
+        double Fx = o[Q_FX] + o[Q_FINX] + (1.0 - rin / rp) * Mp * p->gx + fr[0];
+        double Fy = o[Q_FY] + o[Q_FINY] + (1.0 - rin / rp) * Mp * p->gy + fr[1];
+        double Tz = o[Q_T] + o[Q_TIN];
+        double *n = nw + k * NPIN;
+        for (int i = 0; i < NPIN; ++i) n[i] = q[i];
+        n[P_UX] = q[P_UX] + Fx / Mp;
+        n[P_UY] = q[P_UY] + Fy / Mp;
+        n[P_OM] = q[P_OM] + Tz / Ip;
+        n[P_X] = q[P_X] + q[P_UX];
+        n[P_Y] = q[P_Y] + q[P_UY];
+        n[P_X] -= nx * floor(n[P_X] / nx);
+        n[P_Y] -= ny * floor(n[P_Y] / ny);
+        /* Eq. (Ffin), explicit: carried to the next update */
+        o[Q_FINX] = rin * V * (n[P_UX] - q[P_UX]);
+        o[Q_FINY] = rin * V * (n[P_UY] - q[P_UY]);
+        o[Q_TIN] = Ip * rin / rp * (n[P_OM] - q[P_OM]);
+    }
+    memcpy(st->pin, nw, (size_t)np * NPIN * sizeof(double));
+    free(nw);
+    free(acc);
+    particle_statics(st); /* step 9 */
+}
+
 void orc_destroy(orc_state *st)
 {
     if (!st) return;
+    free(st->pin); free(st->pout);
     free(st->g); free(st->f); free(st->gpost); free(st->fpost);
     for (int k = 0; k < NFIELDS; ++k) free(st->fld[k]);
     free(st);
 }
 
 /* Procedure step 1.  Arrays are [ny][nx], x fastest; cos_theta may be NULL
- * (90 degrees everywhere). */
-int orc_create(const orc_params *p, const double *phi, const double *phi0,
-               const double *cos_theta, const double *ux, const double *uy, orc_state **out)
+ * (90 degrees everywhere).  phi0 and cos_theta describe the stationary solid;
+ * parts holds np free particles, NPIN values each (P_X ... P_COS). */
+int orc_create_particles(const orc_params *p, const double *phi, const double *phi0,
+                         const double *cos_theta, const double *ux, const double *uy, int np,
+                         const double *parts, orc_state **out)
 {
     if (p->nx < 3 || p->ny < 3) return -1;
     orc_state *st = calloc(1, sizeof(orc_state));
@@ -519,14 +718,18 @@ int orc_create(const orc_params *p, const double *phi, const double *phi0,
     st->fpost = malloc(9 * N * sizeof(double));
     for (int k = 0; k < NFIELDS; ++k) st->fld[k] = calloc(N, sizeof(double));
     double **F = st->fld;
+    st->np = np > 0 ? np : 0;
+    st->pin = calloc((size_t)(st->np ? st->np : 1) * NPIN, sizeof(double));
+    st->pout = calloc((size_t)(st->np ? st->np : 1) * NPOUT, sizeof(double));
+    if (st->np) memcpy(st->pin, parts, (size_t)st->np * NPIN * sizeof(double));
     for (long o = 0; o < N; ++o) {
-        double z = clamp01(phi0[o]);
-        F[F_PHI0][o] = z;
-        F[F_PSI][o] = (cos_theta ? cos_theta[o] : 0.0) * z;
+        F[F_ZB][o] = clamp01(phi0[o]);
+        F[F_CB][o] = cos_theta ? cos_theta[o] : 0.0;
         F[F_PHI][o] = phi[o];
         F[F_ULX][o] = ux ? ux[o] : 0.0;
         F[F_ULY][o] = uy ? uy[o] : 0.0;
     }
+    particle_statics(st);
     macro(st, 1);
     save_history(st); /* every d/dt term is zero at the first collision */
     for (long o = 0; o < N; ++o) {
@@ -541,6 +744,22 @@ int orc_create(const orc_params *p, const double *phi, const double *phi0,
     st->steps = 0;
     *out = st;
     return 0;
+}
+
+int orc_create(const orc_params *p, const double *phi, const double *phi0,
+               const double *cos_theta, const double *ux, const double *uy, orc_state **out)
+{
+    return orc_create_particles(p, phi, phi0, cos_theta, ux, uy, 0, NULL, out);
+}
+
+int orc_nparticles(const orc_state *st) { return st->np; }
+
+/* Current particle state (np x NPIN) and outputs of the last update
+ * (np x NPOUT); either may be NULL. */
+void orc_get_particles(const orc_state *st, double *state, double *outputs)
+{
+    if (state && st->np) memcpy(state, st->pin, (size_t)st->np * NPIN * sizeof(double));
+    if (outputs && st->np) memcpy(outputs, st->pout, (size_t)st->np * NPOUT * sizeof(double));
 }
 
 /* Procedure step 2 (collision part) at every node. */
@@ -605,6 +824,7 @@ void orc_step(orc_state *st, long nsteps)
             F[F_PHI][o] = s;
         }
         macro(st, 0);         /* steps 3-6 */
+        if (st->np) particles_update(st); /* steps 7-10 */
         st->steps++;
     }
 }

@@ -45,7 +45,19 @@ class OrcParams(ctypes.Structure):
         ("s3", ctypes.c_double), ("s4", ctypes.c_double),
         ("gx", ctypes.c_double), ("gy", ctypes.c_double), ("rho_ref", ctypes.c_double),
         ("fbx", ctypes.c_double), ("fby", ctypes.c_double), ("solid_eps", ctypes.c_double),
+        ("rep_xi", ctypes.c_double), ("rep_eps", ctypes.c_double),
+        ("wall_x0", ctypes.c_double), ("wall_x1", ctypes.c_double),
+        ("wall_y0", ctypes.c_double), ("wall_y1", ctypes.c_double),
+        ("walls", ctypes.c_int32),
     ]
+
+
+# parameters of the free-particle extension; absent keys take these values
+OPTIONAL = {"rep_xi": 0.0, "rep_eps": 1.0, "wall_x0": 0.0, "wall_x1": 0.0, "wall_y0": 0.0,
+            "wall_y1": 0.0, "walls": 0}
+# particle state columns (input) and per-particle outputs of the last update
+PARTICLE_IN = ["x", "y", "ux", "uy", "omega", "R", "rho_p", "cos_theta"]
+PARTICLE_OUT = ["Fx", "Fy", "T", "Fin_x", "Fin_y", "Tin", "rho_in"]
 
 
 _lib = None
@@ -55,12 +67,19 @@ _D = ctypes.POINTER(ctypes.c_double)
 def lib():
     global _lib
     if _lib is None:
-        if not os.path.exists(LIB):
+        if not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
             build(force=True)
         L = ctypes.CDLL(LIB)
         L.orc_create.argtypes = [ctypes.POINTER(OrcParams), _D, _D, _D, _D, _D,
                                  ctypes.POINTER(ctypes.c_void_p)]
         L.orc_create.restype = ctypes.c_int
+        L.orc_create_particles.argtypes = [ctypes.POINTER(OrcParams), _D, _D, _D, _D, _D,
+                                           ctypes.c_int, _D, ctypes.POINTER(ctypes.c_void_p)]
+        L.orc_create_particles.restype = ctypes.c_int
+        L.orc_nparticles.argtypes = [ctypes.c_void_p]
+        L.orc_nparticles.restype = ctypes.c_int
+        L.orc_get_particles.argtypes = [ctypes.c_void_p, _D, _D]
+        L.orc_repulsion.argtypes = [ctypes.c_double] * 5 + [_D]
         L.orc_destroy.argtypes = [ctypes.c_void_p]
         L.orc_step.argtypes = [ctypes.c_void_p, ctypes.c_long]
         L.orc_steps_done.argtypes = [ctypes.c_void_p]
@@ -101,7 +120,7 @@ def _c64(a) -> np.ndarray:
 def make_params(p: dict) -> OrcParams:
     op = OrcParams()
     for name, _ in OrcParams._fields_:
-        setattr(op, name, p[name])
+        setattr(op, name, p[name] if name in p else OPTIONAL[name])
     return op
 
 
@@ -186,7 +205,9 @@ def mu(params: dict, phi, phi0, psi):
 class Oracle:
     """FP64 CPU stepper.  Fields are numpy arrays of shape (ny, nx)."""
 
-    def __init__(self, params: dict, phi, phi0, cos_theta=None, ux=None, uy=None):
+    def __init__(self, params: dict, phi, phi0, cos_theta=None, ux=None, uy=None, particles=None):
+        """phi0, cos_theta: the stationary solid.  particles: (np, 8) array of
+        x, y, ux, uy, omega, R, rho_p, cos_theta per free particle."""
         phi = _c64(phi)
         ny, nx = phi.shape
         assert params["nx"] == nx and params["ny"] == ny
@@ -197,12 +218,16 @@ class Oracle:
         uxa = None if ux is None else _c64(np.broadcast_to(ux, phi.shape))
         uya = None if uy is None else _c64(np.broadcast_to(uy, phi.shape))
         self._keep += [ct, uxa, uya]
+        parts = np.zeros((0, 8)) if particles is None else _c64(np.reshape(particles, (-1, 8)))
+        self._keep.append(parts)
+        self.np = len(parts)
         op = make_params(self.params)
         h = ctypes.c_void_p()
-        rc = lib().orc_create(ctypes.byref(op), _ptr(self._keep[0]), _ptr(self._keep[1]),
-                              None if ct is None else _ptr(ct),
-                              None if uxa is None else _ptr(uxa),
-                              None if uya is None else _ptr(uya), ctypes.byref(h))
+        rc = lib().orc_create_particles(ctypes.byref(op), _ptr(self._keep[0]), _ptr(self._keep[1]),
+                                        None if ct is None else _ptr(ct),
+                                        None if uxa is None else _ptr(uxa),
+                                        None if uya is None else _ptr(uya), self.np,
+                                        _ptr(parts) if self.np else None, ctypes.byref(h))
         if rc != 0:
             raise ValueError(f"orc_create failed ({rc})")
         self._h = h
@@ -245,6 +270,15 @@ class Oracle:
     def mass(self) -> float:
         return lib().orc_mass(self._h)
 
+    def particles(self):
+        """(state (np, 8), outputs of the last update (np, 7)); columns as in
+        PARTICLE_IN and PARTICLE_OUT."""
+        st = np.zeros((self.np, 8))
+        out = np.zeros((self.np, 7))
+        if self.np:
+            lib().orc_get_particles(self._h, _ptr(st), _ptr(out))
+        return st, out
+
     def energy(self):
         ef, ek = ctypes.c_double(), ctypes.c_double()
         lib().orc_energy(self._h, ctypes.byref(ef), ctypes.byref(ek))
@@ -252,12 +286,12 @@ class Oracle:
 
 
 def macro_node(params: dict, f, rho, muv, phi0, Fx, Fy, Sx, Sy, drx, dry, q_p,
-               u0x=0.0, u0y=0.0, init=False):
+               u0x=0.0, u0y=0.0, init=False, usolx=0.0, usoly=0.0):
     """Steps 5-6 at one node: returns dict u*, f dt, u, s2a, s2b, H, P."""
     L = lib()
     if not getattr(L, "_macro_node_set", False):
         L.orc_macro_node.argtypes = ([ctypes.POINTER(OrcParams), ctypes.c_int, _D]
-                                     + [ctypes.c_double] * 12 + [_D])
+                                     + [ctypes.c_double] * 14 + [_D])
         L._macro_node_set = True
     p = dict(params)
     p.setdefault("nx", 1)
@@ -266,6 +300,14 @@ def macro_node(params: dict, f, rho, muv, phi0, Fx, Fy, Sx, Sy, drx, dry, q_p,
     f = _c64(f)
     out = np.zeros(10)
     L.orc_macro_node(ctypes.byref(op), int(init), _ptr(f), rho, muv, phi0, Fx, Fy, Sx, Sy,
-                     drx, dry, q_p, u0x, u0y, _ptr(out))
+                     drx, dry, q_p, u0x, u0y, usolx, usoly, _ptr(out))
     keys = ["usx", "usy", "ax", "ay", "ux", "uy", "s2a", "s2b", "H", "P"]
     return dict(zip(keys, out))
+
+
+def repulsion(dx: float, dy: float, rsum: float, xi: float, eps: float) -> np.ndarray:
+    """Short-range repulsion of Sec. 4.5 on a particle whose centre is (dx, dy)
+    from the other centre (or from its mirror image across a wall)."""
+    out = np.zeros(2)
+    lib().orc_repulsion(dx, dy, rsum, xi, eps, _ptr(out))
+    return out

@@ -28,7 +28,14 @@ PAPER_DEFAULTS = dict(
     tau_phi=1.0, s0=1.0, s1=1.0, s2=1.0, s3=1.0, s4=1.0,
     gx=0.0, gy=0.0, rho_ref=0.0, fbx=0.0, fby=0.0,
     solid_eps=1e-2,
+    # free particles: repulsion threshold and stiffness (eps <= 0: none),
+    # wall planes for the particle-wall repulsion (bit 0: y0, 1: y1, 2: x0, 3: x1)
+    rep_xi=0.0, rep_eps=0.0, walls=0, wall_x0=0.0, wall_x1=0.0, wall_y0=0.0, wall_y1=0.0,
 )
+
+# Columns of a particle array: centre, translational and angular velocity,
+# radius, density, cos of the contact angle of phase 1 on the particle.
+PARTICLE_COLUMNS = ("x", "y", "ux", "uy", "omega", "R", "rho_p", "cos_theta")
 
 
 def params(nx: int, ny: int, **kw) -> dict:
@@ -51,6 +58,7 @@ class Workload:
     ux: np.ndarray
     uy: np.ndarray
     meta: dict = field(default_factory=dict)
+    particles: np.ndarray | None = None  # (np, 8), columns PARTICLE_COLUMNS
 
     @property
     def shape(self):
@@ -326,3 +334,64 @@ def job_stream(n_jobs: int = 256, seed: int = 4, sides=(128, 256, 512, 1024),
             t += gap / rate_per_s
         jobs.append(JobSpec(j, side, th, ratio, steps, t if rate_per_s is not None else 0.0))
     return jobs
+
+
+# ------------------------------------------------------------ free particles
+def particle(x, y, R, rho_p, theta_deg=90.0, ux=0.0, uy=0.0, omega=0.0) -> list:
+    """One row of a particle array (columns PARTICLE_COLUMNS)."""
+    return [float(x), float(y), float(ux), float(uy), float(omega), float(R), float(rho_p),
+            math.cos(math.radians(theta_deg))]
+
+
+def particles_in_fluid(n: int = 48, parts=None, phi_value: float = 0.0, ux: float = 0.0,
+                       uy: float = 0.0, name: str = "particles in fluid", **kw) -> Workload:
+    """Periodic n x n box of one fluid state phi = phi_value everywhere (0: the
+    50/50 mixture, where the chemical potential and mu_phi0 vanish), uniform
+    velocity, no stationary solid, the given particles."""
+    p = params(n, n, **kw)
+    z = _zeros(n, n)
+    phi = np.full((n, n), float(phi_value))
+    return Workload(name, p, phi, z.copy(), z.copy(), np.full((n, n), float(ux)),
+                    np.full((n, n), float(uy)), {}, np.array(parts if parts is not None else [], float).reshape(-1, 8))
+
+
+def pool_with_particles(nx: int = 1024, ny: int = 2048, n_particles: int = 64, seed: int = 5,
+                        r_range=(12.0, 20.0), rho_ratio_p: float = 2.0, theta_deg: float = 70.0,
+                        rho2: float = 0.1, mu1: float = 0.3, mu_ratio: float = 10.0, g: float = 1e-6,
+                        wall: int = 8, name: str | None = None, **kw) -> Workload:
+    """Gas-liquid-particle box: diffuse walls of `wall` rows/columns on all four
+    sides (90 degrees), a liquid pool filling the lower half, n particles of
+    radius U[r_range] and density rho_ratio_p * rho1 placed without overlap
+    (gap >= 2 D, also from the walls and the pool surface) in the gas above,
+    contact angle theta on every particle, gravity (0, -g) on fluid and
+    particles (rho_ref = rho2), particle-particle and particle-wall repulsion
+    with threshold D/2 and a stiffness that makes the repulsion at half the
+    threshold about ten times a particle's weight."""
+    rng = np.random.default_rng(seed)
+    p = params(nx, ny, **kw)
+    D = p["D"]
+    p.update(rho1=1.0, rho2=rho2, mu1=mu1, mu2=mu1 / mu_ratio, gy=-g, rho_ref=rho2,
+             rep_xi=D / 2.0, rep_eps=2e-3 / g, walls=15,
+             wall_x0=wall - 0.5, wall_x1=nx - wall - 0.5, wall_y0=wall - 0.5, wall_y1=ny - wall - 0.5)
+    x, y = _grid(nx, ny)
+    # distance into the walls, positive inside the solid band
+    zeta = np.maximum.reduce([wall - 0.5 - x, x - (nx - wall - 0.5), wall - 0.5 - y, y - (ny - wall - 0.5)])
+    phi0 = indicator(zeta, D)
+    level = ny / 2.0
+    parts = []
+    tries = 0
+    while len(parts) < n_particles and tries < 200000:
+        tries += 1
+        R = float(rng.uniform(*r_range))
+        xc = float(rng.uniform(wall + R + 2 * D, nx - wall - R - 2 * D))
+        yc = float(rng.uniform(level + R + 2 * D, ny - wall - R - 2 * D))
+        if all(math.hypot(xc - q[0], yc - q[1]) >= R + q[5] + 2 * D for q in parts):
+            parts.append(particle(xc, yc, R, rho_ratio_p * p["rho1"], theta_deg))
+    parts = np.array(parts, float).reshape(-1, 8)
+    phi = (1.0 - phi0) * np.tanh((level - y) / (D / 2.0))
+    for q in parts:  # phi = 0 inside the particles (Sec. 4.5 initial condition)
+        r = np.hypot(x - q[0], y - q[1])
+        phi *= 1.0 - indicator(q[5] - r, D)
+    ct = np.zeros((ny, nx))
+    return Workload(name or f"C5 pool + {len(parts)} particles {nx}x{ny}", p, phi, phi0, ct,
+                    _zeros(nx, ny), _zeros(nx, ny), dict(seed=seed, n_particles=len(parts)), parts)
