@@ -43,7 +43,8 @@ def kernel_source_hash() -> str:
 def run_gpu(workload, storage: str, steps: int, warmup: int, tile: int = 0):
     import torch
     from paper_2311_05097_amd import lbmgls
-    d = lbmgls.Domain(workload.params, *workload.arrays(), storage=storage, tile=tile)
+    d = lbmgls.Domain(workload.params, *workload.arrays(), storage=storage, tile=tile,
+                      particles=workload.particles)
     m0 = d.mass()
     d.step(warmup)
     torch.cuda.synchronize()
@@ -340,6 +341,17 @@ def main():
                                                          measured_traffic("r4096", st, t),
                                                          ceil[("r", st)]),
                                     "finite": e["finite"]}
+        # gas-liquid-particle box (1024 x 2048, 64 free particles): FP32
+        # arithmetic with FP16 and with FP32 storage; the step time includes
+        # the particle kernels (indicator regeneration, FP64 force sums,
+        # update)
+        C5 = W.pool_with_particles()
+        for st in ("fp16dev", "fp32"):
+            t = autotune.best_tile(C5.params, st)
+            e = run_gpu(C5, st, 2000, 100, t)
+            extra[f"C5_{st}"] = {"mlups": round(e["mlups"], 1), "tile": t, "particles": int(len(C5.particles)),
+                                 "ms_per_step": round(e["ms_per_step"], 5),
+                                 "mass_drift": e["mass_drift"], "finite": e["finite"]}
         out["extra"] = extra
     print(json.dumps(out), flush=True)
 

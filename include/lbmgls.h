@@ -79,6 +79,13 @@ typedef struct {
     double gx, gy, rho_ref;/* body force (rho - rho_ref) g                         */
     double fbx, fby;       /* body force (1 - phi0) f_b                            */
     double solid_eps;      /* floor of 1 - phi0 in mu/(rho(1 - phi0)), in (0, 1)   */
+    /* free rigid particles (Sec. 2.4; lbm_create_particles) */
+    double rep_xi, rep_eps;/* Sec. 4.5 repulsion threshold xi and stiffness eps,
+                              lattice units; eps <= 0: no repulsion             */
+    double wall_x0, wall_x1, wall_y0, wall_y1; /* wall planes for the particle-
+                              wall repulsion (mirror image of the particle)    */
+    int32_t np;            /* number of free particles, 0..1024                  */
+    int32_t walls;         /* bit 0: wall_y0, 1: wall_y1, 2: wall_x0, 3: wall_x1 */
 } lbm_params;
 
 typedef struct lbm_domain lbm_domain;
@@ -103,6 +110,37 @@ size_t lbm_workspace_bytes(const lbm_params *p);
 int lbm_create(const lbm_params *p, void *dev_workspace, size_t bytes, void *hip_stream,
                const double *phi, const double *phi0, const double *cos_theta,
                const double *ux, const double *uy, lbm_domain **out);
+
+/* Free rigid disks (Sec. 2.4, procedure steps 7-10): as lbm_create, plus
+ * particles: p->np rows of 8 doubles (x, y, ux, uy, omega, R, rho_p,
+ * cos_theta): centre in lattice units (x along nx), translational and angular
+ * velocity, radius > 0, density > 0, cos of the contact angle of phase 1 on
+ * the particle.  phi0 and cos_theta describe the stationary solid only; each
+ * particle adds its tanh indicator (Sec. 4.5, zero from R + 5 D on) and every
+ * node takes the angle and solid velocity u_p + omega_p x (x - x_p) of the
+ * largest indicator component.  After every step except the first, the
+ * hydrodynamic force and torque (Eq. Ff) are summed in FP64 over each
+ * particle's nodes, the particles advance by explicit Euler (Eq. particle,
+ * internal-fluid corrections of Eq. Ffin, gravity (gx, gy), Sec. 4.5
+ * repulsion) and the indicator is regenerated.  Copies `particles`.
+ * Errors: those of lbm_create; LBM_EINVAL for np outside 0..1024, a NULL
+ * particles array with np > 0 or a non-finite / out-of-range particle;
+ * domains with particles cannot join a batch (LBM_EUNSUPPORTED). */
+int lbm_create_particles(const lbm_params *p, void *dev_workspace, size_t bytes, void *hip_stream,
+                         const double *phi, const double *phi0, const double *cos_theta,
+                         const double *ux, const double *uy, const double *particles,
+                         lbm_domain **out);
+
+/* The particles after the steps taken (np x 8, the columns of
+ * lbm_create_particles) and the outputs of the last particle update (np x 7:
+ * F_f x, y and T_f of Eq. Ff, the internal-fluid corrections F^in x, y and
+ * T^in carried to the next update, and the internal fluid density); either
+ * pointer may be NULL.  A step launch computes the macroscopic fields of its
+ * level before colliding, so the update that belongs to the current level is
+ * done by the next step; this call computes it on demand (one macroscopic
+ * pass, like lbm_read) without changing the domain.  Blocks.
+ * Errors: LBM_EINVAL (NULL domain), LBM_ESTATE (failed finiteness check). */
+int lbm_particles(lbm_domain *d, double *state, double *outputs);
 
 /* Procedure steps 2-6, nsteps >= 0 times: one fused kernel per step (stencils
  * for mu, grad phi, S and F_c from a halo tile, velocity and pressure
@@ -136,14 +174,16 @@ int lbm_energy(lbm_domain *d, double *e_free, double *e_kin);
 /* Steps taken since lbm_create (or the imported state's count). */
 int64_t lbm_steps_done(const lbm_domain *d);
 
-/* Exact checkpoint: the distributions, the history of the previous level and
- * the step count.  lbm_state_bytes gives the host buffer size. Blocks. */
+/* Exact checkpoint: the distributions, the history of the previous level,
+ * the particles (state and carried corrections) and the step count.
+ * lbm_state_bytes gives the host buffer size. Blocks. */
 size_t lbm_state_bytes(const lbm_domain *d);
 int lbm_export_state(lbm_domain *d, void *host_buf, size_t bytes);
 int lbm_import_state(lbm_domain *d, const void *host_buf, size_t bytes);
 
-/* Average duration in milliseconds of the fused step kernel over the last
- * lbm_step call, timed with HIP events on the domain's stream (0 if none). */
+/* Average duration in milliseconds of one step (the fused step kernel, plus
+ * the particle kernels when there are particles) over the last lbm_step
+ * call, timed with HIP events on the domain's stream (0 if none). */
 double lbm_last_step_ms(const lbm_domain *d);
 
 /* Release the handle (not the caller's workspace). */

@@ -48,6 +48,8 @@ struct Layout {
     size_t off_pop[2] = {0, 0}, off_hist[2] = {0, 0};
     size_t off_stat = 0, off_stage = 0, off_part = 0, off_ipart = 0, off_res = 0, off_ires = 0;
     size_t off_job = 0, off_tiles = 0, total = 0;
+    // free particles (np > 0): static solid, owners, rho f planes, FP64 state
+    size_t off_base = 0, off_owner = 0, off_pf = 0, off_parts = 0, off_pout = 0, off_pacc = 0, off_pscr = 0;
 };
 
 size_t real_size(int storage) { return storage == LBM_STORE_FP64 ? 8 : 4; }
@@ -94,6 +96,11 @@ int validate(const lbm_params* p) {
     for (double v : b)
         if (!std::isfinite(v)) return fail(LBM_EINVAL, "body-force parameters must be finite");
     if (!(p->solid_eps > 0.0 && p->solid_eps < 1.0)) return fail(LBM_EINVAL, "solid_eps must lie in (0, 1)");
+    if (p->np < 0 || p->np > 1024) return fail(LBM_EINVAL, "np must lie in 0..1024");
+    const double r[6] = {p->rep_xi, p->rep_eps, p->wall_x0, p->wall_x1, p->wall_y0, p->wall_y1};
+    for (double v : r)
+        if (!std::isfinite(v)) return fail(LBM_EINVAL, "repulsion and wall parameters must be finite");
+    if (p->walls < 0 || p->walls > 15) return fail(LBM_EINVAL, "walls must lie in 0..15");
     return LBM_OK;
 }
 
@@ -122,6 +129,15 @@ Layout layout(const lbm_params& p) {
     L.off_ires = o;  o += up(8 * 8);
     L.off_job = o;   o += up(job_size(p.storage));
     L.off_tiles = o; o += up((size_t)L.ntiles * sizeof(TileEntry));
+    if (p.np > 0) {
+        L.off_base = o;  o += up(2 * L.pitch * R);
+        L.off_owner = o; o += up(L.pitch * 4);
+        L.off_pf = o;    o += up(3 * L.pitch * R);
+        L.off_parts = o; o += up((size_t)p.np * PSTRIDE * 8);
+        L.off_pout = o;  o += up((size_t)p.np * QSTRIDE * 8);
+        L.off_pacc = o;  o += up((size_t)p.np * 5 * 8);
+        L.off_pscr = o;  o += up((size_t)p.np * (PSTRIDE + QSTRIDE) * 8);
+    }
     L.total = o;
     return L;
 }
@@ -221,6 +237,12 @@ void make_job(lbm_domain* d, int32_t n_active, int64_t step0, bool with_out, int
     J.ny = d->p.ny;
     J.n_active = n_active;
     J.tile_base = tile_base;
+    J.np = d->p.np;
+    if (d->p.np > 0) {
+        J.parts = (const double*)(ws + L.off_parts);
+        J.owner = (const int32_t*)(ws + L.off_owner);
+        J.pf = (R*)(ws + L.off_pf);
+    }
     fill_coef<R>(d->p, J.c);
 }
 
@@ -277,9 +299,68 @@ int reduce(lbm_domain* d, bool with_out, double res[NPART], int64_t* imass) {
     return LBM_OK;
 }
 
+// Procedure step 9: phi0, psi and the node owners from the stationary solid
+// and the particles at their current positions, then the Laplacian of psi.
+template <class R>
+int particle_statics(lbm_domain* d) {
+    const Layout& L = d->L;
+    R* st = (R*)(d->ws + L.off_stat);
+    const dim3 grid((unsigned)(((d->p.nx + PT_X - 1) / PT_X) * ((d->p.ny + PT_Y - 1) / PT_Y)));
+    hipLaunchKernelGGL((k_part_static<R>), grid, dim3(PT_X * PT_Y), 0, d->stream,
+                       (const double*)(d->ws + L.off_parts), d->p.np, (const R*)(d->ws + L.off_base), st,
+                       (int32_t*)(d->ws + L.off_owner), L.pitch, d->p.nx, d->p.ny, d->p.D);
+    HIPCHK(hipGetLastError());
+    const int64_t N = (int64_t)d->p.nx * d->p.ny;
+    hipLaunchKernelGGL((k_lap_psi<R>), dim3((unsigned)((N + NT - 1) / NT)), dim3(NT), 0, d->stream, st, L.pitch,
+                       d->p.nx, d->p.ny);
+    HIPCHK(hipGetLastError());
+    return LBM_OK;
+}
+
+// Procedure steps 7, 8 and 10 from the rho f planes of the last macroscopic
+// update: force and torque sums, then the particle update into (nparts, nout)
+// (the particle buffers themselves, or scratch for a preview).
+template <class R>
+int particle_update(lbm_domain* d, double* nparts, double* nout) {
+    const Layout& L = d->L;
+    const lbm_params& p = d->p;
+    hipLaunchKernelGGL((k_part_reduce<R>), dim3((unsigned)p.np), dim3(PR_NT), 0, d->stream,
+                       (const double*)(d->ws + L.off_parts), (const int32_t*)(d->ws + L.off_owner),
+                       (const R*)(d->ws + L.off_pf), (const R*)(d->ws + L.off_stat), L.pitch, p.nx, p.ny, p.D,
+                       (double*)(d->ws + L.off_pacc));
+    HIPCHK(hipGetLastError());
+    PartParams pp;
+    pp.gx = p.gx;
+    pp.gy = p.gy;
+    pp.xi = p.rep_xi;
+    pp.eps = p.rep_eps;
+    pp.wall[0] = p.wall_y0;
+    pp.wall[1] = p.wall_y1;
+    pp.wall[2] = p.wall_x0;
+    pp.wall[3] = p.wall_x1;
+    pp.walls = p.walls;
+    pp.nx = p.nx;
+    pp.ny = p.ny;
+    const unsigned nt = (unsigned)((p.np + 63) / 64 * 64);
+    hipLaunchKernelGGL(k_part_update, dim3(1), dim3(nt), 0, d->stream, (const double*)(d->ws + L.off_parts),
+                       (const double*)(d->ws + L.off_pout), (const double*)(d->ws + L.off_pacc), p.np, pp, nparts,
+                       nout);
+    HIPCHK(hipGetLastError());
+    return LBM_OK;
+}
+
+// Procedure steps 7-10 after a step: the update in place, then the
+// regenerated indicator for the next step.
+template <class R>
+int particle_step(lbm_domain* d) {
+    int rc = particle_update<R>(d, (double*)(d->ws + d->L.off_parts), (double*)(d->ws + d->L.off_pout));
+    if (rc) return rc;
+    return particle_statics<R>(d);
+}
+
 template <class S>
 int create_impl(lbm_domain* d, const double* phi, const double* phi0, const double* cth,
-                const double* ux, const double* uy) {
+                const double* ux, const double* uy, const double* parts) {
     using R = typename S::R;
     const Layout& L = d->L;
     const int64_t N = (int64_t)d->p.nx * d->p.ny;
@@ -297,11 +378,26 @@ int create_impl(lbm_domain* d, const double* phi, const double* phi0, const doub
                           hipMemcpyHostToDevice, d->stream));
     R* st = (R*)(d->ws + L.off_stat);
     const unsigned nb = (unsigned)((N + NT - 1) / NT);
-    hipLaunchKernelGGL((k_static<R>), dim3(nb), dim3(NT), 0, d->stream,
-                       (const double*)(d->ws + L.off_stage), st, L.pitch, N);
-    HIPCHK(hipGetLastError());
-    hipLaunchKernelGGL((k_lap_psi<R>), dim3(nb), dim3(NT), 0, d->stream, st, L.pitch, d->p.nx, d->p.ny);
-    HIPCHK(hipGetLastError());
+    std::vector<double> pstate;
+    if (d->p.np > 0) {
+        // the stationary solid goes to the base planes; phi0, psi and the
+        // owners come from it and the particles
+        hipLaunchKernelGGL((k_part_base<R>), dim3(nb), dim3(NT), 0, d->stream,
+                           (const double*)(d->ws + L.off_stage), (R*)(d->ws + L.off_base), L.pitch, N);
+        HIPCHK(hipGetLastError());
+        pstate.assign(parts, parts + (size_t)d->p.np * PSTRIDE);
+        HIPCHK(hipMemcpyAsync(d->ws + L.off_parts, pstate.data(), pstate.size() * 8, hipMemcpyHostToDevice,
+                              d->stream));
+        HIPCHK(hipMemsetAsync(d->ws + L.off_pout, 0, (size_t)d->p.np * QSTRIDE * 8, d->stream));
+        int rc = particle_statics<R>(d);
+        if (rc) return rc;
+    } else {
+        hipLaunchKernelGGL((k_static<R>), dim3(nb), dim3(NT), 0, d->stream,
+                           (const double*)(d->ws + L.off_stage), st, L.pitch, N);
+        HIPCHK(hipGetLastError());
+        hipLaunchKernelGGL((k_lap_psi<R>), dim3(nb), dim3(NT), 0, d->stream, st, L.pitch, d->p.nx, d->p.ny);
+        HIPCHK(hipGetLastError());
+    }
     int rc = upload_job<S>(d, 0, false);
     if (rc) return rc;
     if ((rc = launch_tiles_ty<S, MODE_INIT>(d, 0))) return rc;
@@ -324,8 +420,12 @@ int step_impl(lbm_domain* d, int64_t nsteps) {
         int rc = upload_job<S>(d, (int32_t)chunk, false);
         if (rc) return rc;
         HIPCHK(hipEventRecord(d->ev0, d->stream));
-        for (int64_t t = 0; t < chunk; ++t)
+        for (int64_t t = 0; t < chunk; ++t) {
             if ((rc = launch_tiles_ty<S, MODE_STEP>(d, (int)t))) return rc;
+            // the particles move after every macroscopic update except the
+            // initial one (the step-0 launch recomputes it)
+            if (d->p.np > 0 && d->steps + t >= 1 && (rc = particle_step<typename S::R>(d))) return rc;
+        }
         HIPCHK(hipEventRecord(d->ev1, d->stream));
         d->steps += chunk;
         done += chunk;
@@ -408,9 +508,10 @@ size_t lbm_workspace_bytes(const lbm_params* p) {
     return layout(*p).total;
 }
 
-int lbm_create(const lbm_params* p, void* dev_workspace, size_t bytes, void* hip_stream,
-               const double* phi, const double* phi0, const double* cos_theta, const double* ux,
-               const double* uy, lbm_domain** out) {
+namespace {
+int create_common(const lbm_params* p, void* dev_workspace, size_t bytes, void* hip_stream,
+                  const double* phi, const double* phi0, const double* cos_theta, const double* ux,
+                  const double* uy, const double* parts, lbm_domain** out) {
     if (!out) return fail(LBM_EINVAL, "out is NULL");
     *out = nullptr;
     int rc = validate(p);
@@ -453,12 +554,73 @@ int lbm_create(const lbm_params* p, void* dev_workspace, size_t bytes, void* hip
         delete d;
         return fail(LBM_EDEVICE, "hipEventCreate failed");
     }
-    rc = dispatch(p->storage, [&](auto s) { return create_impl<decltype(s)>(d, phi, phi0, cos_theta, ux, uy); });
+    rc = dispatch(p->storage,
+                  [&](auto s) { return create_impl<decltype(s)>(d, phi, phi0, cos_theta, ux, uy, parts); });
     if (rc) {
         lbm_destroy(d);
         return rc;
     }
     *out = d;
+    return LBM_OK;
+}
+}  // namespace
+
+int lbm_create(const lbm_params* p, void* dev_workspace, size_t bytes, void* hip_stream,
+               const double* phi, const double* phi0, const double* cos_theta, const double* ux,
+               const double* uy, lbm_domain** out) {
+    if (p && p->np != 0) {
+        if (out) *out = nullptr;
+        return fail(LBM_EINVAL, "np > 0: use lbm_create_particles");
+    }
+    return create_common(p, dev_workspace, bytes, hip_stream, phi, phi0, cos_theta, ux, uy, nullptr, out);
+}
+
+int lbm_create_particles(const lbm_params* p, void* dev_workspace, size_t bytes, void* hip_stream,
+                         const double* phi, const double* phi0, const double* cos_theta, const double* ux,
+                         const double* uy, const double* particles, lbm_domain** out) {
+    if (out) *out = nullptr;
+    if (p && p->np > 0) {
+        if (!particles) return fail(LBM_EINVAL, "particles is NULL");
+        for (int k = 0; k < p->np && k <= 1024; ++k) {
+            const double* q = particles + (size_t)k * PSTRIDE;
+            for (int i = 0; i < PSTRIDE; ++i)
+                if (!std::isfinite(q[i])) return fail(LBM_EINVAL, "non-finite particle " + std::to_string(k));
+            if (!(q[PRAD] > 0.0) || !(q[PRHO] > 0.0) || !(std::fabs(q[PCOS]) <= 1.0))
+                return fail(LBM_EINVAL, "particle " + std::to_string(k) + ": R and rho_p must be positive, "
+                                        "|cos theta| <= 1");
+        }
+    }
+    return create_common(p, dev_workspace, bytes, hip_stream, phi, phi0, cos_theta, ux, uy, particles, out);
+}
+
+int lbm_particles(lbm_domain* d, double* state, double* outputs) {
+    int rc = usable(d);
+    if (rc) return rc;
+    if (d->p.np == 0) return LBM_OK;
+    // A step launch computes the macroscopic fields of its level first; the
+    // particle update that belongs to the current level (procedure steps
+    // 7-10 after steps 3-6) therefore runs after the next launch.  Here it is
+    // computed now from a macroscopic pass at the current level, into scratch,
+    // without changing the domain.
+    const size_t ps = (size_t)d->p.np * PSTRIDE * 8, qs = (size_t)d->p.np * QSTRIDE * 8;
+    const char* src_p = d->ws + d->L.off_parts;
+    const char* src_q = d->ws + d->L.off_pout;
+    if (d->steps >= 1) {
+        rc = dispatch(d->p.storage, [&](auto s) -> int {
+            using S = decltype(s);
+            double res[NPART];
+            int r = reduce<S>(d, false, res, nullptr);
+            if (r) return r;
+            double* scr = (double*)(d->ws + d->L.off_pscr);
+            return particle_update<typename S::R>(d, scr, scr + (size_t)d->p.np * PSTRIDE);
+        });
+        if (rc) return rc;
+        src_p = d->ws + d->L.off_pscr;
+        src_q = src_p + ps;
+    }
+    if (state) HIPCHK(hipMemcpyAsync(state, src_p, ps, hipMemcpyDeviceToHost, d->stream));
+    if (outputs) HIPCHK(hipMemcpyAsync(outputs, src_q, qs, hipMemcpyDeviceToHost, d->stream));
+    HIPCHK(hipStreamSynchronize(d->stream));
     return LBM_OK;
 }
 
@@ -533,7 +695,7 @@ double lbm_last_step_ms(const lbm_domain* d) { return d ? d->last_ms : 0.0; }
 
 size_t lbm_state_bytes(const lbm_domain* d) {
     if (!d) return 0;
-    return 16 + d->L.pop_bytes + d->L.hist_bytes;
+    return 16 + d->L.pop_bytes + d->L.hist_bytes + (size_t)d->p.np * (PSTRIDE + QSTRIDE) * 8;
 }
 
 int lbm_export_state(lbm_domain* d, void* host_buf, size_t bytes) {
@@ -546,6 +708,13 @@ int lbm_export_state(lbm_domain* d, void* host_buf, size_t bytes) {
     HIPCHK(hipMemcpyAsync(h + 16, d->ws + d->L.off_pop[par], d->L.pop_bytes, hipMemcpyDeviceToHost, d->stream));
     HIPCHK(hipMemcpyAsync(h + 16 + d->L.pop_bytes, d->ws + d->L.off_hist[par], d->L.hist_bytes,
                           hipMemcpyDeviceToHost, d->stream));
+    if (d->p.np > 0) {
+        char* hp = h + 16 + d->L.pop_bytes + d->L.hist_bytes;
+        HIPCHK(hipMemcpyAsync(hp, d->ws + d->L.off_parts, (size_t)d->p.np * PSTRIDE * 8, hipMemcpyDeviceToHost,
+                              d->stream));
+        HIPCHK(hipMemcpyAsync(hp + (size_t)d->p.np * PSTRIDE * 8, d->ws + d->L.off_pout,
+                              (size_t)d->p.np * QSTRIDE * 8, hipMemcpyDeviceToHost, d->stream));
+    }
     HIPCHK(hipStreamSynchronize(d->stream));
     return LBM_OK;
 }
@@ -561,6 +730,15 @@ int lbm_import_state(lbm_domain* d, const void* host_buf, size_t bytes) {
     HIPCHK(hipMemcpyAsync(d->ws + d->L.off_pop[par], h + 16, d->L.pop_bytes, hipMemcpyHostToDevice, d->stream));
     HIPCHK(hipMemcpyAsync(d->ws + d->L.off_hist[par], h + 16 + d->L.pop_bytes, d->L.hist_bytes,
                           hipMemcpyHostToDevice, d->stream));
+    if (d->p.np > 0) {
+        const char* hp = h + 16 + d->L.pop_bytes + d->L.hist_bytes;
+        HIPCHK(hipMemcpyAsync(d->ws + d->L.off_parts, hp, (size_t)d->p.np * PSTRIDE * 8, hipMemcpyHostToDevice,
+                              d->stream));
+        HIPCHK(hipMemcpyAsync(d->ws + d->L.off_pout, hp + (size_t)d->p.np * PSTRIDE * 8,
+                              (size_t)d->p.np * QSTRIDE * 8, hipMemcpyHostToDevice, d->stream));
+        const int rc = dispatch(d->p.storage, [&](auto s) { return particle_statics<typename decltype(s)::R>(d); });
+        if (rc) return rc;
+    }
     HIPCHK(hipStreamSynchronize(d->stream));
     d->steps = hdr[0];
     d->failed = false;
@@ -723,6 +901,7 @@ int lbm_batch_add(lbm_batch* b, lbm_domain* d) {
     if (d->batch) return fail(LBM_ESTATE, "domain already in a batch");
     if (d->p.storage != b->storage) return fail(LBM_EINVAL, "storage mode differs from the batch's");
     if (d->L.ty != b->ty) return fail(LBM_EINVAL, "tile shape differs from the batch's");
+    if (d->p.np > 0) return fail(LBM_EUNSUPPORTED, "domains with free particles cannot join a batch");
     if (d->stream != b->stream) return fail(LBM_EINVAL, "domain must use the batch's stream");
     if ((int)b->members.size() >= b->max_members) return fail(LBM_ENOMEM, "batch is full");
     b->members.push_back(d);

@@ -145,10 +145,27 @@ struct Job {
     int32_t nx, ny;
     int32_t n_active;         // launches with t >= n_active leave this job alone
     int32_t tile_base;        // first tile of this job in the tile table
+    int32_t np;               // free particles (0: none)
+    const double* parts;      // [np][PSTRIDE] particle state (Sec. 2.4)
+    const int32_t* owner;     // [pitch] owning particle of each node, -1 if none
+    typename S::R* pf;        // [3][pitch] rho f dt (x, y) and rho at owned nodes
     Coef<typename S::R> c;
 };
 
+// Particle state columns: centre, translational and angular velocity, radius,
+// density, cos of the contact angle of phase 1; per-particle outputs of an
+// update: hydrodynamic force and torque (Eq. Ff), internal-fluid corrections
+// carried to the next update (Eq. Ffin), internal fluid density.
+enum { PX, PY, PUX, PUY, POM, PRAD, PRHO, PCOS, PSTRIDE };
+enum { QFX, QFY, QT, QFINX, QFINY, QTIN, QRHOIN, QSTRIDE };
+constexpr double PCUT = 5.0;  // a particle's indicator is 0 from R + PCUT * D on
+
 // ------------------------------------------------------------------ helpers
+// nearest periodic image of a coordinate difference
+__device__ __forceinline__ double perd(double d, int n) {
+    return d - n * floor(d / n + 0.5);
+}
+
 __device__ __forceinline__ int wrapi(int v, int n) {
     v %= n;
     return v < 0 ? v + n : v;
@@ -386,6 +403,7 @@ __global__ __launch_bounds__(TileCfg<TY>::NT) void k_tile(const Job<S>* __restri
     constexpr int NC = (H1 * W1 + NTH - 1) / NTH; // stage-C points per thread
     __shared__ R sphi[H3 * W3];
     __shared__ R smu[H2 * W2];
+    __shared__ R sz[H2 * W2];                     // phi0 on the stage-B points (particles)
     __shared__ R sSx[H1 * W1];
     __shared__ R sSy[H1 * W1];
     __shared__ R sw[H1 * W1];
@@ -501,6 +519,7 @@ __global__ __launch_bounds__(TileCfg<TY>::NT) void k_tile(const Job<S>* __restri
             const int ly = p / W2, lx = p - ly * W2;
             const int q = (ly + 1) * W3 + (lx + 1);
             smu[p] = chem_pot(c, sphi[q], lap9(sphi, q, W3), bz[k], bpsi[k], blp[k]);
+            sz[p] = bz[k];
         }
     }
     __syncthreads();
@@ -621,12 +640,34 @@ __global__ __launch_bounds__(TileCfg<TY>::NT) void k_tile(const Job<S>* __restri
         R dcx, dcy;
         grad9c(sphi, q3, W3, dcx, dcy);
         const R drx = c.drho * dcx, dry = c.drho * dcy;
-        // total force F = mu grad phi + F_b + F_c, F_c = (-d_y w, d_x w)
-        const R Fx = mu * dpx + ((rho - c.rho_ref) * c.gx + (R(1) - z) * c.fbx) - wy;
-        const R Fy = mu * dpy + ((rho - c.rho_ref) * c.gy + (R(1) - z) * c.fby) + wx;
+        // free particles (Sec. 2.4): the owning particle's solid velocity
+        // u_s = u_p + omega_p x (x - x_p) and the force mu_phi0 grad phi0 of
+        // Eq. (muPhi0) on the nodes a particle owns
+        R usolx = R(0), usoly = R(0), Fpx = R(0), Fpy = R(0);
+        int own = -1;
+        if (J.np) {
+            own = J.owner[o];
+            if (own >= 0) {
+                const double* q = J.parts + own * PSTRIDE;
+                const double rx = perd((double)x - q[PX], nx), ry = perd((double)y - q[PY], ny);
+                usolx = (R)(q[PUX] - q[POM] * ry);
+                usoly = (R)(q[PUY] + q[POM] * rx);
+                const R cth = (R)q[PCOS];
+                R gzx, gzy;
+                grad9(sz, q2, W2, gzx, gzy);
+                const R muz = c.k9s_D * z * ph * ph + c.k3s_D * cth * ph * (R(3) * z * z + ph * ph - R(1))
+                            - c.k3Ds_8 * cth * lap9(sphi, q3, W3);
+                Fpx = muz * gzx;
+                Fpy = muz * gzy;
+            }
+        }
+        // total force F = mu grad phi + mu_phi0 grad phi0 + F_b + F_c, F_c = (-d_y w, d_x w)
+        const R Fx = (mu * dpx + ((rho - c.rho_ref) * c.gx + (R(1) - z) * c.fbx) - wy) + Fpx;
+        const R Fy = (mu * dpy + ((rho - c.rho_ref) * c.gy + (R(1) - z) * c.fby) + wx) + Fpy;
         const R php = hk[0], uxp = hk[1], uyp = hk[2], Sxp = hk[3], Syp = hk[4];
 
-        // Eq. uStar, solid forcing f = phi0 (u_s - u*), Eq. u (u_s = 0)
+        // Eq. uStar, solid forcing f = phi0 (u_s - u*), Eq. u (u_s = 0 unless a
+        // particle owns the node)
         R usx, usy;
         if (first) {
             usx = uxp;
@@ -638,7 +679,12 @@ __global__ __launch_bounds__(TileCfg<TY>::NT) void k_tile(const Job<S>* __restri
             usx = (jx + R(0.5) * Fx) * irho;
             usy = (jy + R(0.5) * Fy) * irho;
         }
-        const R ax = -z * usx, ay = -z * usy;
+        const R ax = z * (usolx - usx), ay = z * (usoly - usy);
+        if (MODE != MODE_INIT && own >= 0) {  // rho f dt and rho for the particle sums
+            J.pf[o] = rho * ax;
+            J.pf[pitch + o] = rho * ay;
+            J.pf[2 * pitch + o] = rho;
+        }
         const R ux = first ? usx : usx + R(0.5) * ax;
         const R uy = first ? usy : usy + R(0.5) * ay;
         // flow relaxation from mu/(rho (1 - phi0)), kept finite in the solid
@@ -815,6 +861,20 @@ __global__ __launch_bounds__(NT) void k_static(const double* __restrict__ in, R*
     st[pitch + o] = (R)(in[2 * pitch + o] * z);
 }
 
+// Stationary solid when there are free particles: phi0 clamped to [0, 1] and
+// cos(theta) as given (input staging planes 1, 2); the particles are added to
+// them every step.
+template <class R>
+__global__ __launch_bounds__(NT) void k_part_base(const double* __restrict__ in, R* __restrict__ base,
+                                                  int64_t pitch, int64_t n) {
+    const int64_t o = (int64_t)blockIdx.x * NT + threadIdx.x;
+    if (o >= n) return;
+    double z = in[pitch + o];
+    z = z < 0.0 ? 0.0 : (z > 1.0 ? 1.0 : z);
+    base[o] = (R)z;
+    base[pitch + o] = (R)in[2 * pitch + o];
+}
+
 // Laplacian of psi (static wetting field), periodic.
 template <class R>
 __global__ __launch_bounds__(NT) void k_lap_psi(R* __restrict__ st, int64_t pitch, int nx, int ny) {
@@ -829,6 +889,194 @@ __global__ __launch_bounds__(NT) void k_lap_psi(R* __restrict__ st, int64_t pitc
     const R ax = (psi[rc + xe] + psi[rc + xw]) + (psi[rn + x] + psi[rs + x]);
     const R dg = (psi[rn + xe] + psi[rn + xw]) + (psi[rs + xe] + psi[rs + xw]);
     st[2 * pitch + o] = (ax - c4) * R(2.0 / 3.0) + (dg - c4) * R(1.0 / 6.0);
+}
+
+// ---------------------------------------------------------- free particles
+// Procedure step 9: the indicator field phi0 = clamp(phi0_static + sum_k
+// phi0_k, 0, 1) with phi0_k the tanh indicator of particle k (nearest periodic
+// image, zero from R + PCUT D on), the owner of every node (the largest
+// component; ties to the static solid, then the lower k) and psi = cos(theta)
+// phi0 with the owner's angle.  One block per 64 x 4 nodes; the particles whose
+// support reaches the block are listed first, in index order, so every node
+// sums the same terms in the same order.
+constexpr int PT_X = 64, PT_Y = 4, PT_MAXLIST = 256;
+template <class R>
+__global__ __launch_bounds__(PT_X * PT_Y) void k_part_static(const double* __restrict__ parts, int np,
+                                                           const R* __restrict__ base, R* __restrict__ st,
+                                                           int32_t* __restrict__ owner, int64_t pitch, int nx,
+                                                           int ny, double D) {
+    __shared__ int list[PT_MAXLIST];
+    __shared__ unsigned char hit[1024];
+    __shared__ int cnt;
+    const int tid = threadIdx.x;
+    const int ntx = (nx + PT_X - 1) / PT_X;
+    const int x0 = (int)(blockIdx.x % ntx) * PT_X, y0 = (int)(blockIdx.x / ntx) * PT_Y;
+    const double cx = x0 + 0.5 * (PT_X - 1), cy = y0 + 0.5 * (PT_Y - 1);
+    for (int k = tid; k < np; k += PT_X * PT_Y) {
+        const double* q = parts + k * PSTRIDE;
+        const double reach = q[PRAD] + PCUT * D;
+        const double dx = fabs(perd(cx - q[PX], nx)), dy = fabs(perd(cy - q[PY], ny));
+        hit[k] = dx <= 0.5 * PT_X + reach && dy <= 0.5 * PT_Y + reach;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        int c = 0;
+        for (int k = 0; k < np && c < PT_MAXLIST; ++k)
+            if (hit[k]) list[c++] = k;
+        cnt = c;
+    }
+    __syncthreads();
+    const int x = x0 + (tid & (PT_X - 1)), y = y0 + tid / PT_X;
+    if (x >= nx || y >= ny) return;
+    const int64_t o = (int64_t)y * nx + x;
+    double sum = (double)base[o], best = sum, cth = (double)base[pitch + o];
+    int own = -1;
+    for (int j = 0; j < cnt; ++j) {
+        const int k = list[j];
+        const double* q = parts + k * PSTRIDE;
+        const double r = hypot(perd(x - q[PX], nx), perd(y - q[PY], ny));
+        const double zk = r < q[PRAD] + PCUT * D ? 0.5 + 0.5 * tanh((q[PRAD] - r) / (D / 2.0)) : 0.0;
+        sum += zk;
+        if (zk > best) {
+            best = zk;
+            own = k;
+            cth = q[PCOS];
+        }
+    }
+    const double z = sum < 0.0 ? 0.0 : (sum > 1.0 ? 1.0 : sum);
+    st[o] = (R)z;
+    st[pitch + o] = (R)(cth * z);
+    owner[o] = own;
+}
+
+// Procedure step 7 (Eq. Ff): per particle (one block each), over the nodes it
+// owns, F_f = -sum rho f dt, T_f = -sum (x - x_p) x rho f dt, and the sums of
+// phi0 rho and phi0 for the internal fluid density.  Fixed-order tree
+// reduction in FP64.
+constexpr int PR_NT = 256;
+template <class R>
+__global__ __launch_bounds__(PR_NT) void k_part_reduce(const double* __restrict__ parts,
+                                                      const int32_t* __restrict__ owner,
+                                                      const R* __restrict__ pf, const R* __restrict__ st,
+                                                      int64_t pitch, int nx, int ny, double D,
+                                                      double* __restrict__ acc) {
+    __shared__ double sh[PR_NT][5];
+    const int k = blockIdx.x, tid = threadIdx.x;
+    const double* q = parts + k * PSTRIDE;
+    const double reach = q[PRAD] + PCUT * D;
+    const int xl = (int)ceil(q[PX] - reach), yl = (int)ceil(q[PY] - reach);
+    int w = (int)floor(q[PX] + reach) - xl + 1, h = (int)floor(q[PY] + reach) - yl + 1;
+    w = w < nx ? w : nx;
+    h = h < ny ? h : ny;
+    double a[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    for (int i = tid; i < w * h; i += PR_NT) {
+        const int x = wrapi(xl + i % w, nx), y = wrapi(yl + i / w, ny);
+        const int64_t o = (int64_t)y * nx + x;
+        if (owner[o] != k) continue;
+        const double fx = (double)pf[o], fy = (double)pf[pitch + o], rho = (double)pf[2 * pitch + o];
+        const double rx = perd(x - q[PX], nx), ry = perd(y - q[PY], ny);
+        const double z = (double)st[o];
+        a[0] -= fx;
+        a[1] -= fy;
+        a[2] -= rx * fy - ry * fx;
+        a[3] += z * rho;
+        a[4] += z;
+    }
+#pragma unroll
+    for (int j = 0; j < 5; ++j) sh[tid][j] = a[j];
+    __syncthreads();
+    for (int s = PR_NT / 2; s > 0; s >>= 1) {
+        if (tid < s) {
+#pragma unroll
+            for (int j = 0; j < 5; ++j) sh[tid][j] += sh[tid + s][j];
+        }
+        __syncthreads();
+    }
+    if (tid < 5) acc[k * 5 + tid] = sh[0][tid];
+}
+
+// Sec. 4.5 repulsion on a particle at (dx, dy) from the other centre (or from
+// its mirror image across a wall); m scales the separation vector.
+__device__ __forceinline__ double rep_scale(double d, double rsum, double xi, double eps) {
+    if (d > rsum + xi) return 0.0;
+    if (d >= rsum) return (rsum + xi - d) * (rsum + xi - d) / eps;
+    return (rsum - d) / eps;
+}
+
+struct PartParams {
+    double gx, gy;                       // gravity acting on the particles
+    double xi, eps;                      // repulsion threshold and stiffness (eps <= 0: none)
+    double wall[4];                      // wall planes y0, y1, x0, x1
+    int walls;                           // bit w: wall[w] present
+    int nx, ny;
+};
+
+// Procedure steps 8 and 10: Eq. (particle) by explicit Euler (dt = 1, every
+// right-hand side at the old level), M_p = rho_p pi R^2, I_p = M_p R^2 / 2,
+// V_p = pi R^2; rho of the internal fluid = sum phi0 rho / sum phi0 over the
+// owned nodes; F^in = rho V_p du_p, T^in = I_p rho / rho_p dw_p carried to the
+// next update.  One block, one thread per particle (np <= 1024): the old state
+// of all particles is read before any thread writes, so the new state may
+// replace it (nparts == parts, nout == out) or go elsewhere.
+__global__ __launch_bounds__(1024) void k_part_update(const double* parts, const double* out,
+                                                    const double* __restrict__ acc, int np, PartParams pp,
+                                                    double* nparts, double* nout) {
+    const int k = threadIdx.x;
+    const double PI = 3.14159265358979323846;
+    double n[PSTRIDE], fin[3] = {0.0, 0.0, 0.0}, o7[QSTRIDE];
+    if (k < np) {
+        const double* q = parts + k * PSTRIDE;
+        const double R = q[PRAD], rp = q[PRHO];
+        const double V = PI * R * R, Mp = rp * V, Ip = Mp * R * R / 2.0;
+        const double* a = acc + k * 5;
+        const double rin = a[4] > 0.0 ? a[3] / a[4] : 0.0;
+        double frx = 0.0, fry = 0.0;
+        if (pp.eps > 0.0) {
+            for (int j = 0; j < np; ++j) {
+                if (j == k) continue;
+                const double* qj = parts + j * PSTRIDE;
+                const double dx = perd(q[PX] - qj[PX], pp.nx), dy = perd(q[PY] - qj[PY], pp.ny);
+                const double m = rep_scale(hypot(dx, dy), R + qj[PRAD], pp.xi, pp.eps);
+                frx += m * dx;
+                fry += m * dy;
+            }
+            for (int w = 0; w < 4; ++w) {
+                if (!(pp.walls >> w & 1)) continue;
+                const double dx = w < 2 ? 0.0 : 2.0 * (q[PX] - pp.wall[w]);
+                const double dy = w < 2 ? 2.0 * (q[PY] - pp.wall[w]) : 0.0;
+                const double m = rep_scale(hypot(dx, dy), 2.0 * R, pp.xi, pp.eps / 2.0);
+                frx += m * dx;
+                fry += m * dy;
+            }
+        }
+        const double* po = out + k * QSTRIDE;
+        const double Fx = a[0] + po[QFINX] + (1.0 - rin / rp) * Mp * pp.gx + frx;
+        const double Fy = a[1] + po[QFINY] + (1.0 - rin / rp) * Mp * pp.gy + fry;
+        const double Tz = a[2] + po[QTIN];
+        for (int i = 0; i < PSTRIDE; ++i) n[i] = q[i];
+        n[PUX] = q[PUX] + Fx / Mp;
+        n[PUY] = q[PUY] + Fy / Mp;
+        n[POM] = q[POM] + Tz / Ip;
+        n[PX] = q[PX] + q[PUX];
+        n[PY] = q[PY] + q[PUY];
+        n[PX] -= pp.nx * floor(n[PX] / pp.nx);
+        n[PY] -= pp.ny * floor(n[PY] / pp.ny);
+        fin[0] = rin * V * (n[PUX] - q[PUX]);
+        fin[1] = rin * V * (n[PUY] - q[PUY]);
+        fin[2] = Ip * rin / rp * (n[POM] - q[POM]);
+        o7[QFX] = a[0];
+        o7[QFY] = a[1];
+        o7[QT] = a[2];
+        o7[QFINX] = fin[0];
+        o7[QFINY] = fin[1];
+        o7[QTIN] = fin[2];
+        o7[QRHOIN] = rin;
+    }
+    __syncthreads();
+    if (k < np) {
+        for (int i = 0; i < PSTRIDE; ++i) nparts[k * PSTRIDE + i] = n[i];
+        for (int i = 0; i < QSTRIDE; ++i) nout[k * QSTRIDE + i] = o7[i];
+    }
 }
 
 // Fixed-order sum of the per-tile partials: res[k] = sum_i part[i][k],

@@ -26,6 +26,7 @@ EXPORTED = [
     "lbm_export_state", "lbm_import_state", "lbm_last_step_ms", "lbm_destroy",
     "lbm_batch_workspace_bytes", "lbm_batch_create", "lbm_batch_add", "lbm_batch_remove",
     "lbm_batch_step", "lbm_batch_size", "lbm_batch_destroy", "lbm_last_error",
+    "lbm_create_particles", "lbm_particles",
 ]
 
 
@@ -46,6 +47,10 @@ class LbmParams(ctypes.Structure):
         ("s3", ctypes.c_double), ("s4", ctypes.c_double),
         ("gx", ctypes.c_double), ("gy", ctypes.c_double), ("rho_ref", ctypes.c_double),
         ("fbx", ctypes.c_double), ("fby", ctypes.c_double), ("solid_eps", ctypes.c_double),
+        ("rep_xi", ctypes.c_double), ("rep_eps", ctypes.c_double),
+        ("wall_x0", ctypes.c_double), ("wall_x1", ctypes.c_double),
+        ("wall_y0", ctypes.c_double), ("wall_y1", ctypes.c_double),
+        ("np", ctypes.c_int32), ("walls", ctypes.c_int32),
     ]
 
 
@@ -94,6 +99,9 @@ def lib():
             "lbm_batch_size": (ctypes.c_int, [_VP]),
             "lbm_batch_destroy": (ctypes.c_int, [_VP]),
             "lbm_last_error": (ctypes.c_char_p, []),
+            "lbm_create_particles": (ctypes.c_int, [P, _VP, ctypes.c_size_t, _VP, _D, _D, _D, _D, _D, _D,
+                                                    ctypes.POINTER(_VP)]),
+            "lbm_particles": (ctypes.c_int, [_VP, _D, _D]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(L, name)
@@ -108,14 +116,15 @@ def _check(rc: int):
         raise LbmError(rc, lib().lbm_last_error().decode())
 
 
-def make_params(p: dict, storage: str | int = "fp32", tile: int = 0) -> LbmParams:
+def make_params(p: dict, storage: str | int = "fp32", tile: int = 0, np_: int = 0) -> LbmParams:
     lp = LbmParams()
     lib().lbm_default_params(ctypes.byref(lp), int(p["nx"]), int(p["ny"]))
     for name, _ in LbmParams._fields_:
-        if name in p and name not in ("storage", "tile"):
+        if name in p and name not in ("storage", "tile", "np"):
             setattr(lp, name, p[name])
     lp.storage = STORAGE[storage] if isinstance(storage, str) else int(storage)
     lp.tile = int(tile)
+    lp.np = int(np_)
     return lp
 
 
@@ -154,8 +163,8 @@ def _arr(a, shape):
     return a, a.ctypes.data_as(_D)
 
 
-def workspace_bytes(params: dict, storage="fp32", tile=0) -> int:
-    lp = make_params(params, storage, tile)
+def workspace_bytes(params: dict, storage="fp32", tile=0, n_particles=0) -> int:
+    lp = make_params(params, storage, tile, n_particles)
     n = lib().lbm_workspace_bytes(ctypes.byref(lp))
     if n == 0:
         raise LbmError(-1, lib().lbm_last_error().decode())
@@ -166,12 +175,18 @@ class Domain:
     """One periodic nx x ny domain resident in GPU memory."""
 
     def __init__(self, params: dict, phi, phi0, cos_theta=None, ux=None, uy=None,
-                 storage: str = "fp32", tile: int = 0, stream=None):
+                 storage: str = "fp32", tile: int = 0, stream=None, particles=None):
+        """particles: (np, 8) array, columns x, y, ux, uy, omega, R, rho_p,
+        cos_theta (free rigid disks); phi0 and cos_theta are then the
+        stationary solid only."""
         self.params = dict(params)
         self.storage = storage
         ny, nx = int(params["ny"]), int(params["nx"])
         self.shape = (ny, nx)
-        self._lp = make_params(params, storage, tile)
+        parts = None if particles is None else np.ascontiguousarray(np.reshape(particles, (-1, 8)),
+                                                                    dtype=np.float64)
+        self.n_particles = 0 if parts is None else len(parts)
+        self._lp = make_params(params, storage, tile, self.n_particles)
         self.nbytes = lib().lbm_workspace_bytes(ctypes.byref(self._lp))
         if self.nbytes == 0:
             raise LbmError(-1, lib().lbm_last_error().decode())
@@ -179,8 +194,12 @@ class Domain:
         self._stream = stream if stream is not None else current_stream_handle()
         keep = [_arr(a, self.shape) for a in (phi, phi0, cos_theta, ux, uy)]
         h = _VP()
-        _check(lib().lbm_create(ctypes.byref(self._lp), _VP(ptr), self.nbytes, self._stream,
-                                *[k[1] for k in keep], ctypes.byref(h)))
+        if self.n_particles:
+            _check(lib().lbm_create_particles(ctypes.byref(self._lp), _VP(ptr), self.nbytes, self._stream,
+                                              *[k[1] for k in keep], parts.ctypes.data_as(_D), ctypes.byref(h)))
+        else:
+            _check(lib().lbm_create(ctypes.byref(self._lp), _VP(ptr), self.nbytes, self._stream,
+                                    *[k[1] for k in keep], ctypes.byref(h)))
         self._h = h
 
     @property
@@ -240,6 +259,15 @@ class Domain:
         ef, ek = ctypes.c_double(), ctypes.c_double()
         _check(lib().lbm_energy(self._h, ctypes.byref(ef), ctypes.byref(ek)))
         return ef.value, ek.value
+
+    def particles(self):
+        """(state (np, 8), outputs of the last update (np, 7)): x, y, ux, uy,
+        omega, R, rho_p, cos_theta; F_f x, y, T_f, F^in x, y, T^in, rho_in."""
+        st = np.zeros((self.n_particles, 8))
+        out = np.zeros((self.n_particles, 7))
+        if self.n_particles:
+            _check(lib().lbm_particles(self._h, st.ctypes.data_as(_D), out.ctypes.data_as(_D)))
+        return st, out
 
     def export_state(self) -> bytes:
         n = lib().lbm_state_bytes(self._h)
