@@ -50,6 +50,8 @@ struct Layout {
     size_t off_job = 0, off_tiles = 0, total = 0;
     // free particles (np > 0): static solid, owners, rho f planes, FP64 state
     size_t off_base = 0, off_owner = 0, off_pf = 0, off_parts = 0, off_pout = 0, off_pacc = 0, off_pscr = 0;
+    size_t off_touch = 0;
+    int pt_blocks = 0;  // 64 x 4 blocks of the particle indicator kernel
 };
 
 size_t real_size(int storage) { return storage == LBM_STORE_FP64 ? 8 : 4; }
@@ -135,8 +137,10 @@ Layout layout(const lbm_params& p) {
         L.off_pf = o;    o += up(3 * L.pitch * R);
         L.off_parts = o; o += up((size_t)p.np * PSTRIDE * 8);
         L.off_pout = o;  o += up((size_t)p.np * QSTRIDE * 8);
-        L.off_pacc = o;  o += up((size_t)p.np * 5 * 8);
+        L.off_pacc = o;  o += up((size_t)p.np * PR_CH * 5 * 8);
         L.off_pscr = o;  o += up((size_t)p.np * (PSTRIDE + QSTRIDE) * 8);
+        L.pt_blocks = ((p.nx + PT_X - 1) / PT_X) * ((p.ny + PT_Y - 1) / PT_Y);
+        L.off_touch = o; o += up((size_t)L.pt_blocks);
     }
     L.total = o;
     return L;
@@ -299,20 +303,18 @@ int reduce(lbm_domain* d, bool with_out, double res[NPART], int64_t* imass) {
     return LBM_OK;
 }
 
-// Procedure step 9: phi0, psi and the node owners from the stationary solid
-// and the particles at their current positions, then the Laplacian of psi.
+// Procedure step 9: phi0, psi, the node owners and the Laplacian of psi from
+// the stationary solid and the particles at their current positions.  With
+// all = true every block recomputes (after create or import); otherwise
+// blocks no particle reaches now or reached last time keep their fields.
 template <class R>
-int particle_statics(lbm_domain* d) {
+int particle_statics(lbm_domain* d, bool all = false) {
     const Layout& L = d->L;
-    R* st = (R*)(d->ws + L.off_stat);
-    const dim3 grid((unsigned)(((d->p.nx + PT_X - 1) / PT_X) * ((d->p.ny + PT_Y - 1) / PT_Y)));
-    hipLaunchKernelGGL((k_part_static<R>), grid, dim3(PT_X * PT_Y), 0, d->stream,
-                       (const double*)(d->ws + L.off_parts), d->p.np, (const R*)(d->ws + L.off_base), st,
-                       (int32_t*)(d->ws + L.off_owner), L.pitch, d->p.nx, d->p.ny, d->p.D);
-    HIPCHK(hipGetLastError());
-    const int64_t N = (int64_t)d->p.nx * d->p.ny;
-    hipLaunchKernelGGL((k_lap_psi<R>), dim3((unsigned)((N + NT - 1) / NT)), dim3(NT), 0, d->stream, st, L.pitch,
-                       d->p.nx, d->p.ny);
+    if (all) HIPCHK(hipMemsetAsync(d->ws + L.off_touch, 1, (size_t)L.pt_blocks, d->stream));
+    hipLaunchKernelGGL((k_part_static<R>), dim3((unsigned)L.pt_blocks), dim3(PT_X * PT_Y), 0, d->stream,
+                       (const double*)(d->ws + L.off_parts), d->p.np, (const R*)(d->ws + L.off_base),
+                       (R*)(d->ws + L.off_stat), (int32_t*)(d->ws + L.off_owner),
+                       (unsigned char*)(d->ws + L.off_touch), L.pitch, d->p.nx, d->p.ny, d->p.D);
     HIPCHK(hipGetLastError());
     return LBM_OK;
 }
@@ -324,7 +326,7 @@ template <class R>
 int particle_update(lbm_domain* d, double* nparts, double* nout) {
     const Layout& L = d->L;
     const lbm_params& p = d->p;
-    hipLaunchKernelGGL((k_part_reduce<R>), dim3((unsigned)p.np), dim3(PR_NT), 0, d->stream,
+    hipLaunchKernelGGL((k_part_reduce<R>), dim3((unsigned)(p.np * PR_CH)), dim3(PR_NT), 0, d->stream,
                        (const double*)(d->ws + L.off_parts), (const int32_t*)(d->ws + L.off_owner),
                        (const R*)(d->ws + L.off_pf), (const R*)(d->ws + L.off_stat), L.pitch, p.nx, p.ny, p.D,
                        (double*)(d->ws + L.off_pacc));
@@ -389,7 +391,7 @@ int create_impl(lbm_domain* d, const double* phi, const double* phi0, const doub
         HIPCHK(hipMemcpyAsync(d->ws + L.off_parts, pstate.data(), pstate.size() * 8, hipMemcpyHostToDevice,
                               d->stream));
         HIPCHK(hipMemsetAsync(d->ws + L.off_pout, 0, (size_t)d->p.np * QSTRIDE * 8, d->stream));
-        int rc = particle_statics<R>(d);
+        int rc = particle_statics<R>(d, true);
         if (rc) return rc;
     } else {
         hipLaunchKernelGGL((k_static<R>), dim3(nb), dim3(NT), 0, d->stream,
@@ -736,7 +738,8 @@ int lbm_import_state(lbm_domain* d, const void* host_buf, size_t bytes) {
                               d->stream));
         HIPCHK(hipMemcpyAsync(d->ws + d->L.off_pout, hp + (size_t)d->p.np * PSTRIDE * 8,
                               (size_t)d->p.np * QSTRIDE * 8, hipMemcpyHostToDevice, d->stream));
-        const int rc = dispatch(d->p.storage, [&](auto s) { return particle_statics<typename decltype(s)::R>(d); });
+        const int rc =
+            dispatch(d->p.storage, [&](auto s) { return particle_statics<typename decltype(s)::R>(d, true); });
         if (rc) return rc;
     }
     HIPCHK(hipStreamSynchronize(d->stream));

@@ -161,8 +161,11 @@ enum { QFX, QFY, QT, QFINX, QFINY, QTIN, QRHOIN, QSTRIDE };
 constexpr double PCUT = 5.0;  // a particle's indicator is 0 from R + PCUT * D on
 
 // ------------------------------------------------------------------ helpers
-// nearest periodic image of a coordinate difference
+// nearest periodic image of a coordinate difference (the division only when
+// the difference is not already within half the period, where the formula
+// returns it unchanged)
 __device__ __forceinline__ double perd(double d, int n) {
+    if (fabs(d) < 0.5 * n) return d;
     return d - n * floor(d / n + 0.5);
 }
 
@@ -895,65 +898,110 @@ __global__ __launch_bounds__(NT) void k_lap_psi(R* __restrict__ st, int64_t pitc
 // Procedure step 9: the indicator field phi0 = clamp(phi0_static + sum_k
 // phi0_k, 0, 1) with phi0_k the tanh indicator of particle k (nearest periodic
 // image, zero from R + PCUT D on), the owner of every node (the largest
-// component; ties to the static solid, then the lower k) and psi = cos(theta)
-// phi0 with the owner's angle.  One block per 64 x 4 nodes; the particles whose
+// component; ties to the static solid, then the lower k), psi = cos(theta)
+// phi0 with the owner's angle, and the Laplacian of psi.  One block per 64 x 8
+// nodes, computing psi on a 1-node halo for the Laplacian; the particles whose
 // support reaches the block are listed first, in index order, so every node
-// sums the same terms in the same order.
-constexpr int PT_X = 64, PT_Y = 4, PT_MAXLIST = 256;
+// sums the same terms in the same order.  A block that no particle reaches now
+// and none reached at its previous call keeps its fields (touched[] remembers).
+constexpr int PT_X = 64, PT_Y = 8, PT_NT = PT_X * PT_Y, PT_MAXLIST = 256;
 template <class R>
-__global__ __launch_bounds__(PT_X * PT_Y) void k_part_static(const double* __restrict__ parts, int np,
+__global__ __launch_bounds__(PT_NT) void k_part_static(const double* __restrict__ parts, int np,
                                                            const R* __restrict__ base, R* __restrict__ st,
-                                                           int32_t* __restrict__ owner, int64_t pitch, int nx,
-                                                           int ny, double D) {
+                                                           int32_t* __restrict__ owner,
+                                                           unsigned char* __restrict__ touched, int64_t pitch,
+                                                           int nx, int ny, double D) {
+    constexpr int HW = PT_X + 2, HH = PT_Y + 2;
+    constexpr int NWV = PT_NT / 64;
     __shared__ int list[PT_MAXLIST];
-    __shared__ unsigned char hit[1024];
+    __shared__ int wcnt[NWV];
     __shared__ int cnt;
-    const int tid = threadIdx.x;
+    __shared__ double spsi[HH * HW];
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int ntx = (nx + PT_X - 1) / PT_X;
     const int x0 = (int)(blockIdx.x % ntx) * PT_X, y0 = (int)(blockIdx.x / ntx) * PT_Y;
     const double cx = x0 + 0.5 * (PT_X - 1), cy = y0 + 0.5 * (PT_Y - 1);
-    for (int k = tid; k < np; k += PT_X * PT_Y) {
-        const double* q = parts + k * PSTRIDE;
-        const double reach = q[PRAD] + PCUT * D;
-        const double dx = fabs(perd(cx - q[PX], nx)), dy = fabs(perd(cy - q[PY], ny));
-        hit[k] = dx <= 0.5 * PT_X + reach && dy <= 0.5 * PT_Y + reach;
-    }
+    if (tid == 0) cnt = 0;
     __syncthreads();
-    if (tid == 0) {
-        int c = 0;
-        for (int k = 0; k < np && c < PT_MAXLIST; ++k)
-            if (hit[k]) list[c++] = k;
-        cnt = c;
+    // candidate list in index order: ballot per wave, prefix over the waves,
+    // one chunk of PT_NT particles at a time
+    for (int k0 = 0; k0 < np; k0 += PT_NT) {
+        const int k = k0 + tid;
+        bool h = false;
+        if (k < np) {
+            const double* q = parts + k * PSTRIDE;
+            const double reach = q[PRAD] + PCUT * D + 1.0;  // + the halo of the Laplacian
+            const double dx = fabs(perd(cx - q[PX], nx)), dy = fabs(perd(cy - q[PY], ny));
+            h = dx <= 0.5 * PT_X + reach && dy <= 0.5 * PT_Y + reach;
+        }
+        const unsigned long long m = __ballot(h);
+        if (lane == 0) wcnt[wv] = __popcll(m);
+        __syncthreads();
+        int before = cnt;
+        for (int w = 0; w < wv; ++w) before += wcnt[w];
+        const int pos = before + __popcll(m & ((1ull << lane) - 1ull));
+        if (h && pos < PT_MAXLIST) list[pos] = k;
+        __syncthreads();
+        if (tid == 0) {
+            int t = cnt;
+            for (int w = 0; w < NWV; ++w) t += wcnt[w];
+            cnt = t < PT_MAXLIST ? t : PT_MAXLIST;
+        }
+        __syncthreads();
+    }
+    const unsigned char was = touched[blockIdx.x];
+    if (cnt == 0 && !was) return;  // uniform: nothing here changed
+    for (int i = tid; i < HH * HW; i += PT_NT) {
+        const int ly = i / HW, lx = i - ly * HW;
+        const int x = wrapi(x0 + lx - 1, nx), y = wrapi(y0 + ly - 1, ny);
+        const int64_t o = (int64_t)y * nx + x;
+        // the indicator in the storage's arithmetic (FP64 for FP64 storage)
+        R sum = base[o], best = sum, cth = base[pitch + o];
+        int own = -1;
+        for (int j = 0; j < cnt; ++j) {
+            const int k = list[j];
+            const double* q = parts + k * PSTRIDE;
+            const R dx = (R)perd(x - q[PX], nx), dy = (R)perd(y - q[PY], ny);
+            const R rad = (R)q[PRAD], cut = rad + (R)(PCUT * D);
+            // clearly outside the support: skip the square root and tanh
+            if (dx * dx + dy * dy > cut * cut * R(1.000001)) continue;
+            const R r = hypot(dx, dy);
+            const R zk = r < cut ? R(0.5) + R(0.5) * tanh((rad - r) / (R)(D / 2.0)) : R(0);
+            sum += zk;
+            if (zk > best) {
+                best = zk;
+                own = k;
+                cth = (R)q[PCOS];
+            }
+        }
+        const R z = sum < R(0) ? R(0) : (sum > R(1) ? R(1) : sum);
+        spsi[i] = (double)(cth * z);  // the stored value, as k_lap_psi would read it
+        const bool inner = lx >= 1 && lx <= PT_X && ly >= 1 && ly <= PT_Y && x0 + lx - 1 < nx && y0 + ly - 1 < ny;
+        if (inner) {
+            st[o] = z;
+            st[pitch + o] = cth * z;
+            owner[o] = own;
+        }
     }
     __syncthreads();
     const int x = x0 + (tid & (PT_X - 1)), y = y0 + tid / PT_X;
+    if (tid == 0) touched[blockIdx.x] = cnt > 0;
     if (x >= nx || y >= ny) return;
-    const int64_t o = (int64_t)y * nx + x;
-    double sum = (double)base[o], best = sum, cth = (double)base[pitch + o];
-    int own = -1;
-    for (int j = 0; j < cnt; ++j) {
-        const int k = list[j];
-        const double* q = parts + k * PSTRIDE;
-        const double r = hypot(perd(x - q[PX], nx), perd(y - q[PY], ny));
-        const double zk = r < q[PRAD] + PCUT * D ? 0.5 + 0.5 * tanh((q[PRAD] - r) / (D / 2.0)) : 0.0;
-        sum += zk;
-        if (zk > best) {
-            best = zk;
-            own = k;
-            cth = q[PCOS];
-        }
-    }
-    const double z = sum < 0.0 ? 0.0 : (sum > 1.0 ? 1.0 : sum);
-    st[o] = (R)z;
-    st[pitch + o] = (R)(cth * z);
-    owner[o] = own;
+    // the same stencil and rounding as k_lap_psi, on the stored psi values
+    const int q = (tid / PT_X + 1) * HW + (tid & (PT_X - 1)) + 1;
+    const R c4 = R(4) * (R)spsi[q];
+    const R ax = ((R)spsi[q + 1] + (R)spsi[q - 1]) + ((R)spsi[q + HW] + (R)spsi[q - HW]);
+    const R dg = ((R)spsi[q + HW + 1] + (R)spsi[q + HW - 1]) + ((R)spsi[q - HW + 1] + (R)spsi[q - HW - 1]);
+    st[2 * pitch + (int64_t)y * nx + x] = (ax - c4) * R(2.0 / 3.0) + (dg - c4) * R(1.0 / 6.0);
 }
 
-// Procedure step 7 (Eq. Ff): per particle (one block each), over the nodes it
-// owns, F_f = -sum rho f dt, T_f = -sum (x - x_p) x rho f dt, and the sums of
-// phi0 rho and phi0 for the internal fluid density.  Fixed-order tree
-// reduction in FP64.
-constexpr int PR_NT = 256;
+// Procedure step 7 (Eq. Ff): per particle, over the nodes it owns,
+// F_f = -sum rho f dt, T_f = -sum (x - x_p) x rho f dt, and the sums of
+// phi0 rho and phi0 for the internal fluid density.  Each particle's support
+// box is cut into PR_CH row bands, one block each; every block writes its own
+// FP64 partials (fixed-order tree reduction), summed in band order by the
+// update.
+constexpr int PR_NT = 256, PR_CH = 8;
 template <class R>
 __global__ __launch_bounds__(PR_NT) void k_part_reduce(const double* __restrict__ parts,
                                                       const int32_t* __restrict__ owner,
@@ -961,20 +1009,27 @@ __global__ __launch_bounds__(PR_NT) void k_part_reduce(const double* __restrict_
                                                       int64_t pitch, int nx, int ny, double D,
                                                       double* __restrict__ acc) {
     __shared__ double sh[PR_NT][5];
-    const int k = blockIdx.x, tid = threadIdx.x;
+    const int k = blockIdx.x / PR_CH, band = blockIdx.x % PR_CH, tid = threadIdx.x;
     const double* q = parts + k * PSTRIDE;
     const double reach = q[PRAD] + PCUT * D;
     const int xl = (int)ceil(q[PX] - reach), yl = (int)ceil(q[PY] - reach);
     int w = (int)floor(q[PX] + reach) - xl + 1, h = (int)floor(q[PY] + reach) - yl + 1;
-    w = w < nx ? w : nx;
-    h = h < ny ? h : ny;
+    // a box narrower than the domain holds each node once, and there the plain
+    // difference is the nearest periodic image
+    const bool wrap_x = w >= nx, wrap_y = h >= ny;
+    w = wrap_x ? nx : w;
+    h = wrap_y ? ny : h;
+    const int r0 = band * h / PR_CH, r1 = (band + 1) * h / PR_CH;
     double a[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-    for (int i = tid; i < w * h; i += PR_NT) {
-        const int x = wrapi(xl + i % w, nx), y = wrapi(yl + i / w, ny);
+    for (int i = tid; i < (r1 - r0) * w; i += PR_NT) {
+        const int iy = r0 + i / w, ix = i - (i / w) * w;
+        const int xu = xl + ix, yu = yl + iy;
+        const int x = wrapi(xu, nx), y = wrapi(yu, ny);
         const int64_t o = (int64_t)y * nx + x;
         if (owner[o] != k) continue;
         const double fx = (double)pf[o], fy = (double)pf[pitch + o], rho = (double)pf[2 * pitch + o];
-        const double rx = perd(x - q[PX], nx), ry = perd(y - q[PY], ny);
+        const double rx = wrap_x ? perd(x - q[PX], nx) : xu - q[PX];
+        const double ry = wrap_y ? perd(y - q[PY], ny) : yu - q[PY];
         const double z = (double)st[o];
         a[0] -= fx;
         a[1] -= fy;
@@ -992,7 +1047,7 @@ __global__ __launch_bounds__(PR_NT) void k_part_reduce(const double* __restrict_
         }
         __syncthreads();
     }
-    if (tid < 5) acc[k * 5 + tid] = sh[0][tid];
+    if (tid < 5) acc[(int64_t)blockIdx.x * 5 + tid] = sh[0][tid];
 }
 
 // Sec. 4.5 repulsion on a particle at (dx, dy) from the other centre (or from
@@ -1028,13 +1083,19 @@ __global__ __launch_bounds__(1024) void k_part_update(const double* parts, const
         const double* q = parts + k * PSTRIDE;
         const double R = q[PRAD], rp = q[PRHO];
         const double V = PI * R * R, Mp = rp * V, Ip = Mp * R * R / 2.0;
-        const double* a = acc + k * 5;
+        double a[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+        for (int c = 0; c < PR_CH; ++c)
+            for (int j = 0; j < 5; ++j) a[j] += acc[((int64_t)k * PR_CH + c) * 5 + j];
         const double rin = a[4] > 0.0 ? a[3] / a[4] : 0.0;
         double frx = 0.0, fry = 0.0;
         if (pp.eps > 0.0) {
             for (int j = 0; j < np; ++j) {
                 if (j == k) continue;
                 const double* qj = parts + j * PSTRIDE;
+                // far pairs (no image within the threshold) contribute nothing
+                const double lim = R + qj[PRAD] + pp.xi;
+                const double ax = fabs(q[PX] - qj[PX]), ay = fabs(q[PY] - qj[PY]);
+                if ((ax > lim && pp.nx - ax > lim) || (ay > lim && pp.ny - ay > lim)) continue;
                 const double dx = perd(q[PX] - qj[PX], pp.nx), dy = perd(q[PY] - qj[PY], pp.ny);
                 const double m = rep_scale(hypot(dx, dy), R + qj[PRAD], pp.xi, pp.eps);
                 frx += m * dx;
