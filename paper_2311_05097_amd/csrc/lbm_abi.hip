@@ -263,8 +263,12 @@ template <class S, int TY, int MODE>
 int launch_tiles(lbm_domain* d, int t) {
     const Job<S>* J = (const Job<S>*)(d->ws + d->L.off_job);
     const TileEntry* T = (const TileEntry*)(d->ws + d->L.off_tiles);
-    hipLaunchKernelGGL((k_tile<S, TY, MODE>), dim3(d->L.ntiles), dim3(TileCfg<TY>::NT), 0, d->stream, J, T,
-                       d->L.ntiles, t);
+    if (MODE != MODE_INIT && d->p.np > 0)
+        hipLaunchKernelGGL((k_tile<S, TY, MODE, true>), dim3(d->L.ntiles), dim3(TileCfg<TY>::NT), 0, d->stream, J,
+                           T, d->L.ntiles, t);
+    else
+        hipLaunchKernelGGL((k_tile<S, TY, MODE>), dim3(d->L.ntiles), dim3(TileCfg<TY>::NT), 0, d->stream, J, T,
+                           d->L.ntiles, t);
     HIPCHK(hipGetLastError());
     return LBM_OK;
 }

@@ -388,7 +388,9 @@ struct TileCfg {
 // on the 3-node halo ring, the static fields on the 2-node halo, the previous
 // velocity on the 1-node halo -- are issued in one phase (A) before the first
 // barrier, so their latencies overlap.
-template <class S, int TY, int MODE>
+// PART: the domain has free particles (their branch and its LDS are compiled
+// only into this variant, so the plain kernel keeps its register budget).
+template <class S, int TY, int MODE, bool PART = false>
 __global__ __launch_bounds__(TileCfg<TY>::NT) void k_tile(const Job<S>* __restrict__ jobs,
                                                          const TileEntry* __restrict__ tiles, int ntiles,
                                                          int t) {
@@ -406,7 +408,7 @@ __global__ __launch_bounds__(TileCfg<TY>::NT) void k_tile(const Job<S>* __restri
     constexpr int NC = (H1 * W1 + NTH - 1) / NTH; // stage-C points per thread
     __shared__ R sphi[H3 * W3];
     __shared__ R smu[H2 * W2];
-    __shared__ R sz[H2 * W2];                     // phi0 on the stage-B points (particles)
+    __shared__ R sz[PART ? H2 * W2 : 1];          // phi0 on the stage-B points (particles)
     __shared__ R sSx[H1 * W1];
     __shared__ R sSy[H1 * W1];
     __shared__ R sw[H1 * W1];
@@ -522,7 +524,7 @@ __global__ __launch_bounds__(TileCfg<TY>::NT) void k_tile(const Job<S>* __restri
             const int ly = p / W2, lx = p - ly * W2;
             const int q = (ly + 1) * W3 + (lx + 1);
             smu[p] = chem_pot(c, sphi[q], lap9(sphi, q, W3), bz[k], bpsi[k], blp[k]);
-            sz[p] = bz[k];
+            if (PART) sz[p] = bz[k];
         }
     }
     __syncthreads();
@@ -648,7 +650,7 @@ __global__ __launch_bounds__(TileCfg<TY>::NT) void k_tile(const Job<S>* __restri
         // Eq. (muPhi0) on the nodes a particle owns
         R usolx = R(0), usoly = R(0), Fpx = R(0), Fpy = R(0);
         int own = -1;
-        if (J.np) {
+        if (PART) {
             own = J.owner[o];
             if (own >= 0) {
                 const double* q = J.parts + own * PSTRIDE;
@@ -683,7 +685,7 @@ __global__ __launch_bounds__(TileCfg<TY>::NT) void k_tile(const Job<S>* __restri
             usy = (jy + R(0.5) * Fy) * irho;
         }
         const R ax = z * (usolx - usx), ay = z * (usoly - usy);
-        if (MODE != MODE_INIT && own >= 0) {  // rho f dt and rho for the particle sums
+        if (PART && own >= 0) {  // rho f dt and rho for the particle sums
             J.pf[o] = rho * ax;
             J.pf[pitch + o] = rho * ay;
             J.pf[2 * pitch + o] = rho;
