@@ -144,10 +144,11 @@ def copy_calibrate(nbytes: int = 1 << 30, reps: int = 5):
     print(json.dumps({"copy_bytes_read": nbytes, "copy_bytes_written": nbytes, "reps": reps}))
 
 
-def serve_bench(args):
+def serve_bench(args, runs=None):
     """Served jobs/s and p50/p99 latency of the drop-on-slab job stream:
-    plain FP32 per-job path versus continuous batching in FP32, FP16 and BF16
-    storage, on the same seeded stream and arrival times."""
+    plain FP32 per-job path versus continuous batching (FP32, FP16 and BF16
+    storage by default), on the same seeded stream and arrival times.
+    Returns the result object."""
     import numpy as np
     from paper_2311_05097_amd import lbmgls, serve
     from paper_2311_05097_amd import workloads as W
@@ -192,7 +193,8 @@ def serve_bench(args):
     print(f"[serve] {len(refs)} FP64 references done, {time.perf_counter() - t_start:.0f} s",
           file=sys.stderr, flush=True)
     modes = []
-    runs = [("solo", "fp32")] + [("batched", s) for s in ("fp32", "fp16dev", "bf16dev")]
+    if runs is None:
+        runs = [("solo", "fp32")] + [("batched", s) for s in ("fp32", "fp16dev", "bf16dev")]
     for kind, st in runs:
         if kind == "solo":
             stats = serve.run_solo(jobs, storage=st, tile=8, keep_phi=True,
@@ -237,7 +239,7 @@ def serve_bench(args):
                    "budget_GiB": args.budget_gib, "tick_steps": args.tick, "best_mode": best["mode"]},
         "modes": modes,
     }
-    print(json.dumps(out), flush=True)
+    return out
 
 
 def main():
@@ -249,6 +251,7 @@ def main():
     ap.add_argument("--tile", type=int, default=0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extra", action="store_true")
+    ap.add_argument("--no-serve", action="store_true", help="skip the served-jobs leg of the default run")
     ap.add_argument("--copy-calibrate", action="store_true")
     ap.add_argument("--workload", default="c2", choices=["c2", "r4096"],
                     help="c2: the 1024^2 cylinder + drop case (default); r4096: the same physics "
@@ -276,7 +279,7 @@ def main():
         copy_calibrate()
         return
     if args.serve:
-        serve_bench(args)
+        print(json.dumps(serve_bench(args)), flush=True)
         return
 
     from paper_2311_05097_amd import workloads as W
@@ -316,6 +319,18 @@ def main():
     }
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline()
+    if not args.no_serve:
+        # the served-jobs half of the metric, on a 64-job stream (the full
+        # 256-job comparison of four modes is `bench.py --serve`)
+        sargs = argparse.Namespace(jobs=64, ratio_range=(10.0, 200.0), rate_factor=2.0, budget_gib=4,
+                                   tick=500, ref_every=8, jobs_out="")
+        sv = serve_bench(sargs, runs=[("solo", "fp32"), ("batched", "fp16dev")])
+        keep = ("mode", "jobs_done", "jobs_failed", "jobs_per_s", "p50_latency_s", "p99_latency_s",
+                "max_rel_mass_drift", "max_rel_phi_err_vs_fp64")
+        out["serving"] = {"metric": "served jobs/s", "unit": "jobs/s", "value": sv["value"],
+                          "vs_plain_fp32_per_job": sv["vs_plain_fp32_per_job"],
+                          "workload": sv["config"]["workload"],
+                          "modes": [{k: m[k] for k in keep} for m in sv["modes"]]}
     if not args.no_extra:
         extra = {}
         for st in ("fp64", "fp16dev", "bf16dev"):
