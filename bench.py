@@ -253,9 +253,10 @@ def main():
     ap.add_argument("--no-extra", action="store_true")
     ap.add_argument("--no-serve", action="store_true", help="skip the served-jobs leg of the default run")
     ap.add_argument("--copy-calibrate", action="store_true")
-    ap.add_argument("--workload", default="c2", choices=["c2", "r4096"],
+    ap.add_argument("--workload", default="c2", choices=["c2", "r4096", "c5"],
                     help="c2: the 1024^2 cylinder + drop case (default); r4096: the same physics "
-                         "on 4096^2 (working set far above the last-level cache)")
+                         "on 4096^2 (working set far above the last-level cache); c5: the 1024 x 2048 "
+                         "pool with 64 free particles (step time includes the particle kernels)")
     ap.add_argument("--serve", action="store_true", help="served-jobs benchmark instead")
     ap.add_argument("--jobs", type=int, default=256)
     ap.add_argument("--ratio-range", type=float, nargs=2, default=(10.0, 1000.0))
@@ -284,7 +285,7 @@ def main():
 
     from paper_2311_05097_amd import workloads as W
     from paper_2311_05097_amd import autotune
-    w = W.config2() if args.workload == "c2" else W.roofline_grid()
+    w = {"c2": W.config2, "r4096": W.roofline_grid, "c5": W.pool_with_particles}[args.workload]()
     R = W.roofline_grid()
     nw, nr = w.params["nx"] * w.params["ny"], R.params["nx"] * R.params["ny"]
     # copy ceilings first, in a fresh allocator state
@@ -307,8 +308,9 @@ def main():
         "vs_baseline": None,
         "dtype": DTYPE[args.storage],
         "data": "synthetic (seeded tanh geometry, no dataset)",
-        "config": {"workload": w.name + ": periodic, cylinder R=%g, drop R=%g, theta=60, "
-                               "rho ratio 100, mu ratio 50, g=1e-6" % (w.meta["Rp"], w.meta["R0"]),
+        "config": {"workload": (w.name + ": periodic, cylinder R=%g, drop R=%g, theta=60, "
+                                "rho ratio 100, mu ratio 50, g=1e-6" % (w.meta["Rp"], w.meta["R0"])
+                                if "Rp" in w.meta else w.name),
                    "nx": w.params["nx"], "ny": w.params["ny"], "storage": args.storage,
                    "tile": f"64x{tile}"},
         "roofline": roofline(args.storage, r["nodes"], r["kernel_ms"],

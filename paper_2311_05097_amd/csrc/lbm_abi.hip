@@ -347,8 +347,7 @@ int particle_update(lbm_domain* d, double* nparts, double* nout) {
     pp.walls = p.walls;
     pp.nx = p.nx;
     pp.ny = p.ny;
-    const unsigned nt = (unsigned)((p.np + 63) / 64 * 64);
-    hipLaunchKernelGGL(k_part_update, dim3(1), dim3(nt), 0, d->stream, (const double*)(d->ws + L.off_parts),
+    hipLaunchKernelGGL(k_part_update, dim3(1), dim3(PU_NT), 0, d->stream, (const double*)(d->ws + L.off_parts),
                        (const double*)(d->ws + L.off_pout), (const double*)(d->ws + L.off_pacc), p.np, pp, nparts,
                        nout);
     HIPCHK(hipGetLastError());

@@ -1072,15 +1072,48 @@ struct PartParams {
 // right-hand side at the old level), M_p = rho_p pi R^2, I_p = M_p R^2 / 2,
 // V_p = pi R^2; rho of the internal fluid = sum phi0 rho / sum phi0 over the
 // owned nodes; F^in = rho V_p du_p, T^in = I_p rho / rho_p dw_p carried to the
-// next update.  One block, one thread per particle (np <= 1024): the old state
-// of all particles is read before any thread writes, so the new state may
-// replace it (nparts == parts, nout == out) or go elsewhere.
-__global__ __launch_bounds__(1024) void k_part_update(const double* parts, const double* out,
-                                                    const double* __restrict__ acc, int np, PartParams pp,
-                                                    double* nparts, double* nout) {
-    const int k = threadIdx.x;
+// next update.  One block of 1024 threads (np <= 1024): the particle-particle
+// repulsion of particle k is split over PU_SPLIT(np) threads (partner j in
+// steps of the split), whose partial sums thread k adds in a fixed order.  The
+// old state of all particles is read before any thread writes, so the new
+// state may replace it (nparts == parts, nout == out) or go elsewhere.
+constexpr int PU_NT = 1024;
+__host__ __device__ constexpr int pu_split(int np) {
+    int s = 1;
+    while (s * 2 * np <= PU_NT) s *= 2;
+    return s;
+}
+__global__ __launch_bounds__(PU_NT) void k_part_update(const double* parts, const double* out,
+                                                     const double* __restrict__ acc, int np, PartParams pp,
+                                                     double* nparts, double* nout) {
+    __shared__ double rx[PU_NT], ry[PU_NT];
+    const int t = threadIdx.x, split = pu_split(np);
+    {
+        const int k = t / split, part = t % split;
+        double sx = 0.0, sy = 0.0;
+        if (k < np && pp.eps > 0.0) {
+            const double* q = parts + k * PSTRIDE;
+            const double R = q[PRAD];
+            for (int j = part; j < np; j += split) {
+                if (j == k) continue;
+                const double* qj = parts + j * PSTRIDE;
+                // far pairs (no image within the threshold) contribute nothing
+                const double lim = R + qj[PRAD] + pp.xi;
+                const double ax = fabs(q[PX] - qj[PX]), ay = fabs(q[PY] - qj[PY]);
+                if ((ax > lim && pp.nx - ax > lim) || (ay > lim && pp.ny - ay > lim)) continue;
+                const double dx = perd(q[PX] - qj[PX], pp.nx), dy = perd(q[PY] - qj[PY], pp.ny);
+                const double m = rep_scale(hypot(dx, dy), R + qj[PRAD], pp.xi, pp.eps);
+                sx += m * dx;
+                sy += m * dy;
+            }
+        }
+        rx[t] = sx;
+        ry[t] = sy;
+    }
+    __syncthreads();
+    const int k = t;
     const double PI = 3.14159265358979323846;
-    double n[PSTRIDE], fin[3] = {0.0, 0.0, 0.0}, o7[QSTRIDE];
+    double n[PSTRIDE], o7[QSTRIDE];
     if (k < np) {
         const double* q = parts + k * PSTRIDE;
         const double R = q[PRAD], rp = q[PRHO];
@@ -1091,17 +1124,9 @@ __global__ __launch_bounds__(1024) void k_part_update(const double* parts, const
         const double rin = a[4] > 0.0 ? a[3] / a[4] : 0.0;
         double frx = 0.0, fry = 0.0;
         if (pp.eps > 0.0) {
-            for (int j = 0; j < np; ++j) {
-                if (j == k) continue;
-                const double* qj = parts + j * PSTRIDE;
-                // far pairs (no image within the threshold) contribute nothing
-                const double lim = R + qj[PRAD] + pp.xi;
-                const double ax = fabs(q[PX] - qj[PX]), ay = fabs(q[PY] - qj[PY]);
-                if ((ax > lim && pp.nx - ax > lim) || (ay > lim && pp.ny - ay > lim)) continue;
-                const double dx = perd(q[PX] - qj[PX], pp.nx), dy = perd(q[PY] - qj[PY], pp.ny);
-                const double m = rep_scale(hypot(dx, dy), R + qj[PRAD], pp.xi, pp.eps);
-                frx += m * dx;
-                fry += m * dy;
+            for (int p = 0; p < split; ++p) {
+                frx += rx[k * split + p];
+                fry += ry[k * split + p];
             }
             for (int w = 0; w < 4; ++w) {
                 if (!(pp.walls >> w & 1)) continue;
@@ -1124,15 +1149,12 @@ __global__ __launch_bounds__(1024) void k_part_update(const double* parts, const
         n[PY] = q[PY] + q[PUY];
         n[PX] -= pp.nx * floor(n[PX] / pp.nx);
         n[PY] -= pp.ny * floor(n[PY] / pp.ny);
-        fin[0] = rin * V * (n[PUX] - q[PUX]);
-        fin[1] = rin * V * (n[PUY] - q[PUY]);
-        fin[2] = Ip * rin / rp * (n[POM] - q[POM]);
         o7[QFX] = a[0];
         o7[QFY] = a[1];
         o7[QT] = a[2];
-        o7[QFINX] = fin[0];
-        o7[QFINY] = fin[1];
-        o7[QTIN] = fin[2];
+        o7[QFINX] = rin * V * (n[PUX] - q[PUX]);
+        o7[QFINY] = rin * V * (n[PUY] - q[PUY]);
+        o7[QTIN] = Ip * rin / rp * (n[POM] - q[POM]);
         o7[QRHOIN] = rin;
     }
     __syncthreads();
