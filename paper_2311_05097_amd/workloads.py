@@ -146,6 +146,25 @@ def cylinder_drop(n: int = 1024, Rp: float = 128.0, R0: float = 160.0, theta_deg
                     dict(Rp=Rp, R0=R0, theta_deg=theta_deg))
 
 
+def drop_on_cylinder(n: int = 256, Rp: float = 50.0, R0: float = 50.0, theta_deg: float = 90.0,
+                     rho_ratio: float = 10.0, name: str | None = None, **kw) -> Workload:
+    """The drop-on-cylinder case of Sec. 4.2: an n x n box (the paper's
+    [-L/2, L/2] x [-L/4, 3L/4], cylinder at the origin, i.e. lattice (n/2,
+    n/4)), cylinder radius Rp, a drop of radius R0 centred on the top of the
+    cylinder surface, phi = (1 - phi0) tanh((R0 - r)/(D/2)); rho1 = 1,
+    rho2 = rho1 / rho_ratio and the Sec. 4.1 parameters otherwise.  Periodic in
+    y as well (the paper's top and bottom walls are far from the drop)."""
+    p = params(n, n, **kw)
+    p.update(rho1=1.0, rho2=1.0 / rho_ratio)
+    x, y = _grid(n, n)
+    cx, cy = n / 2.0, n / 4.0
+    phi0 = indicator(Rp - np.hypot(x - cx, y - cy), p["D"])
+    phi = (1.0 - phi0) * np.tanh((R0 - np.hypot(x - cx, y - (cy + Rp))) / (p["D"] / 2.0))
+    ct = np.full((n, n), math.cos(math.radians(theta_deg)))
+    return Workload(name or f"drop on cylinder {n}x{n} theta={theta_deg:g}", p, phi, phi0, ct,
+                    _zeros(n, n), _zeros(n, n), dict(Rp=Rp, R0=R0, theta_deg=theta_deg, cx=cx, cy=cy))
+
+
 def config2() -> Workload:
     """1024 x 1024, cylinder R = 128 at the centre, drop R = 160 on top,
     60 degrees, density ratio 100, viscosity ratio 50, gravity 1e-6."""
