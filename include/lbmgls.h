@@ -114,8 +114,10 @@ int lbm_create(const lbm_params *p, void *dev_workspace, size_t bytes, void *hip
 /* Free rigid disks (Sec. 2.4, procedure steps 7-10): as lbm_create, plus
  * particles: p->np rows of 8 doubles (x, y, ux, uy, omega, R, rho_p,
  * cos_theta): centre in lattice units (x along nx), translational and angular
- * velocity, radius > 0, density > 0, cos of the contact angle of phase 1 on
- * the particle.  phi0 and cos_theta describe the stationary solid only; each
+ * velocity, radius > 0, density, cos of the contact angle of phase 1 on the
+ * particle.  A density <= 0 marks a solid of prescribed motion (e.g. a
+ * rotating cylinder): its velocity and angular velocity are held, its centre
+ * advances with its velocity, and its force and torque are still reported.  phi0 and cos_theta describe the stationary solid only; each
  * particle adds its tanh indicator (Sec. 4.5, zero from R + 5 D on) and every
  * node takes the angle and solid velocity u_p + omega_p x (x - x_p) of the
  * largest indicator component.  After every step except the first, the
@@ -124,7 +126,7 @@ int lbm_create(const lbm_params *p, void *dev_workspace, size_t bytes, void *hip
  * internal-fluid corrections of Eq. Ffin, gravity (gx, gy), Sec. 4.5
  * repulsion) and the indicator is regenerated.  Copies `particles`.
  * Errors: those of lbm_create; LBM_EINVAL for np outside 0..1024, a NULL
- * particles array with np > 0 or a non-finite / out-of-range particle;
+ * particles array with np > 0 or a non-finite particle, R <= 0, |cos| > 1;
  * domains with particles cannot join a batch (LBM_EUNSUPPORTED). */
 int lbm_create_particles(const lbm_params *p, void *dev_workspace, size_t bytes, void *hip_stream,
                          const double *phi, const double *phi0, const double *cos_theta,

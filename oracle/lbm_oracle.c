@@ -69,6 +69,10 @@
  *            - the particles move after each macroscopic update of the loop,
  *              not after the initial one (procedure: step 1, then steps 2-10
  *              repeated); the next update of the fields sees the new phi0.
+ *            - a particle with rho_p <= 0 has prescribed motion (SURVEY's
+ *              prescribed-motion solids, e.g. the rotating inner cylinder of
+ *              Sec. 4.5): u_p and omega_p are held, the centre advances with
+ *              u_p, F_f and T_f are still summed (reported), F^in = T^in = 0;
  *            - repulsion (Sec. 4.5) as printed, particle-particle with the
  *              nearest periodic image, particle-wall against optional
  *              axis-aligned wall planes (mirror image of the particle);
@@ -662,23 +666,24 @@ static void particles_update(orc_state *st)
             repulsion(dx, dy, 2.0 * R, p->rep_xi, p->rep_eps / 2.0, t);
             fr[0] += t[0]; fr[1] += t[1];
         }
-        /* Eq. (particle), explicit Euler with dt = 1 */
-        double Fx = o[Q_FX] + o[Q_FINX] + (1.0 - rin / rp) * Mp * p->gx + fr[0];
-        double Fy = o[Q_FY] + o[Q_FINY] + (1.0 - rin / rp) * Mp * p->gy + fr[1];
-        double Tz = o[Q_T] + o[Q_TIN];
         double *n = nw + k * NPIN;
         for (int i = 0; i < NPIN; ++i) n[i] = q[i];
-        n[P_UX] = q[P_UX] + Fx / Mp;
-        n[P_UY] = q[P_UY] + Fy / Mp;
-        n[P_OM] = q[P_OM] + Tz / Ip;
+        if (rp > 0.0) { /* Eq. (particle), explicit Euler with dt = 1 */
+            double Fx = o[Q_FX] + o[Q_FINX] + (1.0 - rin / rp) * Mp * p->gx + fr[0];
+            double Fy = o[Q_FY] + o[Q_FINY] + (1.0 - rin / rp) * Mp * p->gy + fr[1];
+            double Tz = o[Q_T] + o[Q_TIN];
+            n[P_UX] = q[P_UX] + Fx / Mp;
+            n[P_UY] = q[P_UY] + Fy / Mp;
+            n[P_OM] = q[P_OM] + Tz / Ip;
+        }
         n[P_X] = q[P_X] + q[P_UX];
         n[P_Y] = q[P_Y] + q[P_UY];
         n[P_X] -= nx * floor(n[P_X] / nx);
         n[P_Y] -= ny * floor(n[P_Y] / ny);
         /* Eq. (Ffin), explicit: carried to the next update */
-        o[Q_FINX] = rin * V * (n[P_UX] - q[P_UX]);
-        o[Q_FINY] = rin * V * (n[P_UY] - q[P_UY]);
-        o[Q_TIN] = Ip * rin / rp * (n[P_OM] - q[P_OM]);
+        o[Q_FINX] = rp > 0.0 ? rin * V * (n[P_UX] - q[P_UX]) : 0.0;
+        o[Q_FINY] = rp > 0.0 ? rin * V * (n[P_UY] - q[P_UY]) : 0.0;
+        o[Q_TIN] = rp > 0.0 ? Ip * rin / rp * (n[P_OM] - q[P_OM]) : 0.0;
     }
     memcpy(st->pin, nw, (size_t)np * NPIN * sizeof(double));
     free(nw);

@@ -590,9 +590,8 @@ int lbm_create_particles(const lbm_params* p, void* dev_workspace, size_t bytes,
             const double* q = particles + (size_t)k * PSTRIDE;
             for (int i = 0; i < PSTRIDE; ++i)
                 if (!std::isfinite(q[i])) return fail(LBM_EINVAL, "non-finite particle " + std::to_string(k));
-            if (!(q[PRAD] > 0.0) || !(q[PRHO] > 0.0) || !(std::fabs(q[PCOS]) <= 1.0))
-                return fail(LBM_EINVAL, "particle " + std::to_string(k) + ": R and rho_p must be positive, "
-                                        "|cos theta| <= 1");
+            if (!(q[PRAD] > 0.0) || !(std::fabs(q[PCOS]) <= 1.0))
+                return fail(LBM_EINVAL, "particle " + std::to_string(k) + ": R must be positive, |cos theta| <= 1");
         }
     }
     return create_common(p, dev_workspace, bytes, hip_stream, phi, phi0, cos_theta, ux, uy, particles, out);

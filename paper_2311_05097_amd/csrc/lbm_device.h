@@ -1072,7 +1072,9 @@ struct PartParams {
 // right-hand side at the old level), M_p = rho_p pi R^2, I_p = M_p R^2 / 2,
 // V_p = pi R^2; rho of the internal fluid = sum phi0 rho / sum phi0 over the
 // owned nodes; F^in = rho V_p du_p, T^in = I_p rho / rho_p dw_p carried to the
-// next update.  One block of 1024 threads (np <= 1024): the particle-particle
+// next update.  A particle with rho_p <= 0 has prescribed motion: u_p and
+// omega_p are held, the centre advances, F_f and T_f are still reported.
+// One block of 1024 threads (np <= 1024): the particle-particle
 // repulsion of particle k is split over PU_SPLIT(np) threads (partner j in
 // steps of the split), whose partial sums thread k adds in a fixed order.  The
 // old state of all particles is read before any thread writes, so the new
@@ -1138,13 +1140,15 @@ __global__ __launch_bounds__(PU_NT) void k_part_update(const double* parts, cons
             }
         }
         const double* po = out + k * QSTRIDE;
-        const double Fx = a[0] + po[QFINX] + (1.0 - rin / rp) * Mp * pp.gx + frx;
-        const double Fy = a[1] + po[QFINY] + (1.0 - rin / rp) * Mp * pp.gy + fry;
-        const double Tz = a[2] + po[QTIN];
         for (int i = 0; i < PSTRIDE; ++i) n[i] = q[i];
-        n[PUX] = q[PUX] + Fx / Mp;
-        n[PUY] = q[PUY] + Fy / Mp;
-        n[POM] = q[POM] + Tz / Ip;
+        if (rp > 0.0) {  // free; rho_p <= 0: prescribed motion, u_p and omega_p held
+            const double Fx = a[0] + po[QFINX] + (1.0 - rin / rp) * Mp * pp.gx + frx;
+            const double Fy = a[1] + po[QFINY] + (1.0 - rin / rp) * Mp * pp.gy + fry;
+            const double Tz = a[2] + po[QTIN];
+            n[PUX] = q[PUX] + Fx / Mp;
+            n[PUY] = q[PUY] + Fy / Mp;
+            n[POM] = q[POM] + Tz / Ip;
+        }
         n[PX] = q[PX] + q[PUX];
         n[PY] = q[PY] + q[PUY];
         n[PX] -= pp.nx * floor(n[PX] / pp.nx);
@@ -1152,9 +1156,9 @@ __global__ __launch_bounds__(PU_NT) void k_part_update(const double* parts, cons
         o7[QFX] = a[0];
         o7[QFY] = a[1];
         o7[QT] = a[2];
-        o7[QFINX] = rin * V * (n[PUX] - q[PUX]);
-        o7[QFINY] = rin * V * (n[PUY] - q[PUY]);
-        o7[QTIN] = Ip * rin / rp * (n[POM] - q[POM]);
+        o7[QFINX] = rp > 0.0 ? rin * V * (n[PUX] - q[PUX]) : 0.0;
+        o7[QFINY] = rp > 0.0 ? rin * V * (n[PUY] - q[PUY]) : 0.0;
+        o7[QTIN] = rp > 0.0 ? Ip * rin / rp * (n[POM] - q[POM]) : 0.0;
         o7[QRHOIN] = rin;
     }
     __syncthreads();

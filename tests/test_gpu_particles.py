@@ -30,15 +30,17 @@ def rel(a, b):
 
 
 def particle_case(nx=67, ny=45):
-    """Two-phase box (liquid below y = 22), gravity, three particles of
+    """Two-phase box (liquid below y = 22), gravity, three free particles of
     different radius, density and angle, one spinning, one close to a wall
-    plane; repulsion on.  Ragged in both directions for every tile shape."""
+    plane, and one of prescribed motion (rho_p <= 0); repulsion on.  Ragged
+    in both directions for every tile shape."""
     p = W.params(nx, ny, rho2=0.5, mu2=0.05, gy=-2e-5, rho_ref=0.5, rep_xi=2.0, rep_eps=50.0,
                  walls=15, wall_x0=1.5, wall_x1=nx - 1.5, wall_y0=1.5, wall_y1=ny - 1.5)
     D = p["D"]
     parts = np.array([W.particle(14.3, 21.2, 5.5, 1.6, 60.0, ux=0.002),
                       W.particle(40.5, 26.9, 7.0, 0.9, 120.0, omega=1e-3),
-                      W.particle(58.0, 9.2, 6.0, 1.2, 90.0, uy=-0.001)])
+                      W.particle(58.0, 9.2, 6.0, 1.2, 90.0, uy=-0.001),
+                      W.particle(30.0, 36.0, 4.0, -1.0, 75.0, ux=0.001, omega=-2e-3)])  # prescribed motion
     y, x = np.mgrid[0:ny, 0:nx].astype(float)
     phi = np.tanh((22.0 - y) / (D / 2))
     for q in parts:

@@ -71,3 +71,53 @@ def test_drop_on_cylinder_equilibrium_height(gpu, theta):
     ref = h_max(theta, w.meta["Rp"], w.meta["R0"])
     print(f"\ntheta {theta}: H {H:.3f}, equal-area H_max {ref:.3f} ({(H - ref) / ref:+.2%})")
     assert abs(H - ref) <= 0.02 * ref
+
+
+def _couette_run(gpu, n, Rin, Rout, steps, storage="fp32"):
+    om = 0.02 / Rin
+    p = W.params(n, n)
+    y, x = np.mgrid[0:n, 0:n].astype(float)
+    c = n / 2.0
+    r = np.hypot(x - c, y - c)
+    zb = W.indicator(r - Rout, p["D"])
+    d = gpu.Domain(p, np.zeros((n, n)), zb, storage=storage,
+                   particles=[W.particle(c, c, Rin, -1.0, 90.0, omega=om)])
+    d.step(steps)
+    _, ux, uy, _ = d.read()
+    st, out = d.particles()
+    ut = (-(y - c) * ux + (x - c) * uy) / np.maximum(r, 1e-9)
+    mid = 0.5 * (Rin + Rout)
+    return om, out[0, 2], float(ut[np.abs(r - mid) < 0.5].mean()), mid, p["mu1"]
+
+
+def _torque(mu, om, a, b):
+    """Circular Couette flow: torque per unit depth on the inner cylinder."""
+    return 4.0 * math.pi * mu * om * a * a * b * b / (b * b - a * a)
+
+
+def _utheta(om, a, b, r):
+    return om * a * a / (b * b - a * a) * (b * b / r - r)
+
+
+def test_rotating_cylinder_couette(gpu):
+    """Prescribed rotation (rho_p <= 0) of an inner cylinder inside a
+    stationary ring: steady circular Couette flow.  The diffuse solid
+    boundaries act as walls displaced by a few nodes, so the torque on the
+    cylinder (the particle force sum of Eq. Ff) converges to the sharp-wall
+    value at first order in D/R (the error halves when the radii double), and
+    with the displacement fitted from the torque the Couette profile
+    u = A r + B / r predicts the mid-gap velocity."""
+    from scipy.optimize import brentq
+    errs = []
+    for n, Rin, Rout, steps in ((256, 40.0, 112.0, 30000), (512, 80.0, 224.0, 110000)):
+        om, T, umid, mid, mu = _couette_run(gpu, n, Rin, Rout, steps)
+        sharp = _torque(mu, om, Rin, Rout)
+        errs.append(abs(T) / sharp - 1.0)
+        dlt = brentq(lambda d: _torque(mu, om, Rin + d, Rout - d) - abs(T), -5.0, 15.0)
+        pred = _utheta(om, Rin + dlt, Rout - dlt, mid)
+        print(f"\nR_in {Rin}: torque {abs(T):.4f} vs sharp {sharp:.4f} ({errs[-1]:+.1%}), wall shift {dlt:.2f}, "
+              f"mid-gap u {umid:.5f} vs {pred:.5f}")
+        assert T < 0
+        assert 0.5 < dlt < 6.0
+        assert abs(umid - pred) <= 0.03 * pred
+    assert errs[1] < 0.6 * errs[0] and errs[1] < 0.15

@@ -227,3 +227,37 @@ def test_particle_at_interface_moves_into_the_wetting_phase(orc):
     pa, pb = a.field("phi"), b.field("phi")
     mirror = (2 * (3 * H // 4) - np.arange(H)) % H
     assert np.abs(pa + pb[mirror, :]).max() < 1e-11
+
+
+def test_prescribed_rotation_couette_torque_balance(orc):
+    """A solid of prescribed motion (rho_p <= 0: the rotating inner cylinder
+    of Sec. 4.5) inside a stationary ring: its angular velocity is held, the
+    fluid turns with it and reaches a steady circular Couette flow, and at
+    steady state the torque the fluid exerts on the cylinder (reported by the
+    particle update, Eq. Ff) balances the torque of the ring's penalty force
+    on the fluid (angular-momentum balance: viscous and pressure forces are
+    internal)."""
+    n, Rin, Rout, om = 64, 10.0, 28.0, 2e-3
+    p = W.params(n, n)
+    y, x = np.mgrid[0:n, 0:n].astype(float)
+    c = n / 2.0
+    r = np.hypot(x - c, y - c)
+    zb = W.indicator(r - Rout, p["D"])
+    o = orc.Oracle(p, np.zeros((n, n)), zb, particles=[W.particle(c, c, Rin, -1.0, 90.0, omega=om)])
+    o.step(3000)
+    st, out = o.particles()
+    assert st[0, 4] == om and st[0, 2] == 0.0 and st[0, 3] == 0.0 and st[0, 0] == c
+    own = o.field("owner") < 0
+    rho = o.field("rho")
+    fx, fy = rho * o.field("asx"), rho * o.field("asy")
+    t_ring = ((x - c) * fy - (y - c) * fx)[own].sum()  # torque of the ring on the fluid
+    assert out[0, 2] < 0  # the fluid brakes the cylinder
+    # balanced up to what is left of the start-up transient (the slowest
+    # viscous mode of the gap decays over ~(Rout - Rin)^2 / (nu pi^2) ~ 330
+    # steps; a wrong sign or lever arm would be off by 50-200%)
+    assert abs(out[0, 2] - t_ring) <= 1e-3 * abs(t_ring)
+    # and the fluid between turns with the cylinder, fastest near it
+    _, ux, uy, _ = o.read()
+    ut = (-(y - c) * ux + (x - c) * uy) / np.maximum(r, 1e-9)
+    prof = [ut[np.abs(r - rr) < 0.5].mean() for rr in (14.0, 19.0, 24.0)]
+    assert prof[0] > prof[1] > prof[2] > 0
