@@ -69,15 +69,24 @@
  *            - the particles move after each macroscopic update of the loop,
  *              not after the initial one (procedure: step 1, then steps 2-10
  *              repeated); the next update of the fields sees the new phi0.
- *            - a particle with rho_p <= 0 has prescribed motion (SURVEY's
- *              prescribed-motion solids, e.g. the rotating inner cylinder of
- *              Sec. 4.5): u_p and omega_p are held, the centre advances with
- *              u_p, F_f and T_f are still summed (reported), F^in = T^in = 0;
+ *            - a particle with rho_p <= 0 has prescribed motion (e.g. the
+ *              rotating inner cylinder of Sec. 4.5): u_p and omega_p are
+ *              held, the centre advances with u_p, F_f and T_f are still
+ *              summed (reported), F^in = T^in = 0;
  *            - repulsion (Sec. 4.5) as printed, particle-particle with the
  *              nearest periodic image, particle-wall against optional
  *              axis-aligned wall planes (mirror image of the particle);
  *              none when the stiffness parameter is <= 0.
- *   Periodic in x and y.
+ *   R-WALL   with bounce_y set, no-flux walls halfway outside the first and
+ *            last rows (y = -1/2 and ny - 1/2): populations that would
+ *            cross a wall are reflected into the opposite direction at the
+ *            same node (halfway bounce-back, neutral wetting); the
+ *            finite-difference stencils read mirrored ghost rows (-1 -> 0,
+ *            -2 -> 1, ...): scalars unchanged, the mass flux S as the
+ *            gradient of such a scalar (S_y changes sign) and the lagged
+ *            velocity in T of F_c odd in both components (no slip); free
+ *            particles measure distances in y without the periodic image.
+ *   Periodic in x, and in y unless bounce_y is set.
  */
 #include <math.h>
 #include <omp.h>
@@ -101,6 +110,7 @@ typedef struct {
     double rep_xi, rep_eps;      /* repulsion threshold and stiffness (Sec. 4.5) */
     double wall_x0, wall_x1, wall_y0, wall_y1; /* wall planes for the repulsion  */
     int32_t walls;               /* bit 0: y0, 1: y1, 2: x0, 3: x1 present  */
+    int32_t bounce_y;            /* R-WALL: no-flux walls below and above   */
 } orc_params;
 
 /* One free rigid disk (Sec. 2.4): centre, translational and angular velocity,
@@ -306,13 +316,29 @@ static inline long nb(int nx, int ny, int x, int y, int i)
     return (long)yy * nx + xx;
 }
 
-void orc_grad(int nx, int ny, const double *chi, double *gx, double *gy)
+/* Neighbour value in direction i: periodic, or with walls (R-WALL) the
+ * mirrored ghost row times the field's parity under the reflection. */
+static inline double nbv(const double *chi, int nx, int ny, int walls, double parity, int x, int y, int i)
+{
+    int xx = ((x + CX[i]) % nx + nx) % nx;
+    int yy = y + CY[i];
+    double sg = 1.0;
+    if (walls && (yy < 0 || yy >= ny)) {
+        yy = yy < 0 ? -1 - yy : 2 * ny - 1 - yy;
+        sg = parity;
+    } else {
+        yy = (yy % ny + ny) % ny;
+    }
+    return sg * chi[(long)yy * nx + xx];
+}
+
+static void grad_b(int nx, int ny, int walls, double parity, const double *chi, double *gx, double *gy)
 {
     for (int y = 0; y < ny; ++y)
         for (int x = 0; x < nx; ++x) {
             double sx = 0.0, sy = 0.0;
             for (int i = 0; i < 9; ++i) {
-                double v = chi[nb(nx, ny, x, y, i)];
+                double v = nbv(chi, nx, ny, walls, parity, x, y, i);
                 sx += WT[i] * CX[i] * v;
                 sy += WT[i] * CY[i] * v;
             }
@@ -321,15 +347,25 @@ void orc_grad(int nx, int ny, const double *chi, double *gx, double *gy)
         }
 }
 
-void orc_lap(int nx, int ny, const double *chi, double *lap)
+static void lap_b(int nx, int ny, int walls, const double *chi, double *lap)
 {
     for (int y = 0; y < ny; ++y)
         for (int x = 0; x < nx; ++x) {
             long o = (long)y * nx + x;
             double s = 0.0;
-            for (int i = 0; i < 9; ++i) s += WT[i] * (chi[nb(nx, ny, x, y, i)] - chi[o]);
+            for (int i = 0; i < 9; ++i) s += WT[i] * (nbv(chi, nx, ny, walls, 1.0, x, y, i) - chi[o]);
             lap[o] = 6.0 * s; /* 2 / c_s^2 with c_s^2 = 1/3 */
         }
+}
+
+void orc_grad(int nx, int ny, const double *chi, double *gx, double *gy)
+{
+    grad_b(nx, ny, 0, 1.0, chi, gx, gy);
+}
+
+void orc_lap(int nx, int ny, const double *chi, double *lap)
+{
+    lap_b(nx, ny, 0, chi, lap);
 }
 
 /* ---- Eq. (potential): chemical potential, wetting terms through psi ---- */
@@ -339,8 +375,8 @@ void orc_mu(const orc_params *p, const double *phi, const double *phi0, const do
     const int nx = p->nx, ny = p->ny;
     const long N = (long)nx * ny;
     double *lphi = malloc(N * sizeof(double)), *lpsi = malloc(N * sizeof(double));
-    orc_lap(nx, ny, phi, lphi);
-    orc_lap(nx, ny, psi, lpsi);
+    lap_b(nx, ny, p->bounce_y, phi, lphi);
+    lap_b(nx, ny, p->bounce_y, psi, lpsi);
     const double s = p->sigma, D = p->D;
     for (long o = 0; o < N; ++o) {
         double f = phi[o], z = phi0[o], q = psi[o];
@@ -455,6 +491,30 @@ void orc_macro_node(const orc_params *p, int init, const double f[9], double rho
 /* Procedure steps 3-6 at the current time from phi (already in the state),
  * the flow distributions and the lagged velocity.  If init != 0, u* is the
  * given velocity and P = 0 (R-INIT). */
+/* T_alpha,beta = (S_alpha u_beta - u_alpha S_beta)/2 of R-FC at node (x, y),
+ * periodic in x.  Rows outside the domain are periodic images, or with walls
+ * (R-WALL) ghost rows built from the mirrored node: S is the gradient of a
+ * scalar mirrored evenly (S_x even, S_y odd) and the no-slip velocity is odd
+ * in both components. */
+static double t_ab(const orc_state *st, int a, int b, int x, int y)
+{
+    const int nx = st->p.nx, ny = st->p.ny;
+    double sS[2] = {1.0, 1.0}, sU[2] = {1.0, 1.0};
+    x = (x % nx + nx) % nx;
+    if (st->p.bounce_y && (y < 0 || y >= ny)) {
+        y = y < 0 ? -1 - y : 2 * ny - 1 - y;
+        sS[1] = -1.0;
+        sU[0] = sU[1] = -1.0;
+    } else {
+        y = (y % ny + ny) % ny;
+    }
+    const long o = (long)y * nx + x;
+    double *const *F = st->fld;
+    const double S[2] = {sS[0] * F[F_SX][o], sS[1] * F[F_SY][o]};
+    const double u[2] = {sU[0] * F[F_ULX][o], sU[1] * F[F_ULY][o]};
+    return (S[a] * u[b] - u[a] * S[b]) / 2.0;
+}
+
 static void macro(orc_state *st, int init)
 {
     const orc_params *p = &st->p;
@@ -470,37 +530,32 @@ static void macro(orc_state *st, int init)
     }
     /* chemical potential, gradients, consistent mass flux S = M grad(mu)(rho1-rho2)/2 */
     orc_mu(p, F[F_PHI], F[F_PHI0], F[F_PSI], F[F_MU]);
-    orc_grad(nx, ny, F[F_PHI], F[F_DPHIX], F[F_DPHIY]);
-    orc_grad(nx, ny, F[F_RHO], F[F_DRHOX], F[F_DRHOY]);
+    const int W = p->bounce_y;
+    grad_b(nx, ny, W, 1.0, F[F_PHI], F[F_DPHIX], F[F_DPHIY]);
+    grad_b(nx, ny, W, 1.0, F[F_RHO], F[F_DRHOX], F[F_DRHOY]);
     double *gmx = malloc(N * sizeof(double)), *gmy = malloc(N * sizeof(double));
-    orc_grad(nx, ny, F[F_MU], gmx, gmy);
+    grad_b(nx, ny, W, 1.0, F[F_MU], gmx, gmy);
     for (long o = 0; o < N; ++o) {
         F[F_SX][o] = p->M * gmx[o] * (p->rho1 - p->rho2) / 2.0;
         F[F_SY][o] = p->M * gmy[o] * (p->rho1 - p->rho2) / 2.0;
     }
     /* step 4: F_c = div(S u - u S)/2 with the lagged velocity (R-FC):
      * F_c,beta = d_alpha T_alpha,beta,  T_alpha,beta = (S_alpha u_beta - u_alpha S_beta)/2 */
-    double *T[2][2], *dTx = malloc(N * sizeof(double)), *dTy = malloc(N * sizeof(double));
-    for (int a = 0; a < 2; ++a)
-        for (int b = 0; b < 2; ++b) T[a][b] = malloc(N * sizeof(double));
-    for (long o = 0; o < N; ++o) {
-        double S[2] = {F[F_SX][o], F[F_SY][o]}, u[2] = {F[F_ULX][o], F[F_ULY][o]};
-        for (int a = 0; a < 2; ++a)
-            for (int b = 0; b < 2; ++b) T[a][b][o] = (S[a] * u[b] - u[a] * S[b]) / 2.0;
-    }
-    for (long o = 0; o < N; ++o) { F[F_FCX][o] = 0.0; F[F_FCY][o] = 0.0; }
-    for (int b = 0; b < 2; ++b) {
-        double *out = b == 0 ? F[F_FCX] : F[F_FCY];
-        orc_grad(nx, ny, T[0][b], dTx, dTy);
-        for (long o = 0; o < N; ++o) out[o] += dTx[o]; /* d_x T_x,beta */
-        orc_grad(nx, ny, T[1][b], dTx, dTy);
-        for (long o = 0; o < N; ++o) out[o] += dTy[o]; /* d_y T_y,beta */
-    }
+    for (int y = 0; y < ny; ++y)
+        for (int x = 0; x < nx; ++x) {
+            for (int b = 0; b < 2; ++b) {
+                double sx = 0.0, sy = 0.0;
+                for (int i = 0; i < 9; ++i) sx += WT[i] * CX[i] * t_ab(st, 0, b, x + CX[i], y + CY[i]);
+                for (int i = 0; i < 9; ++i) sy += WT[i] * CY[i] * t_ab(st, 1, b, x + CX[i], y + CY[i]);
+                /* d_x T_x,beta + d_y T_y,beta, 1 / c_s^2 = 3 */
+                F[b == 0 ? F_FCX : F_FCY][(long)y * nx + x] = 3.0 * sx + 3.0 * sy;
+            }
+        }
     /* mu_phi0 (Eq. muPhi0) where a free particle owns the node (R-PART) */
     double *gzx = malloc(N * sizeof(double)), *gzy = malloc(N * sizeof(double));
     double *lphi = malloc(N * sizeof(double));
-    orc_grad(nx, ny, F[F_PHI0], gzx, gzy);
-    orc_lap(nx, ny, F[F_PHI], lphi);
+    grad_b(nx, ny, W, 1.0, F[F_PHI0], gzx, gzy);
+    lap_b(nx, ny, W, F[F_PHI], lphi);
     for (long o = 0; o < N; ++o) {
         F[F_MUZ][o] = 0.0;
         int k = (int)F[F_OWN][o];
@@ -532,9 +587,7 @@ static void macro(orc_state *st, int init)
         F[F_S2A][o] = out[6]; F[F_S2B][o] = out[7]; F[F_H][o] = out[8];
         F[F_P][o] = out[9];
     }
-    for (int a = 0; a < 2; ++a)
-        for (int b = 0; b < 2; ++b) free(T[a][b]);
-    free(dTx); free(dTy); free(gmx); free(gmy);
+    free(gmx); free(gmy);
 }
 
 /* Save the values of the current level as the history of the next one. */
@@ -563,6 +616,12 @@ static double per(double d, int n)
     return d - n * floor(d / n + 0.5);
 }
 
+/* The same in y, which is not periodic between walls (R-WALL). */
+static double pery(const orc_params *p, double d)
+{
+    return p->bounce_y ? d : per(d, p->ny);
+}
+
 /* Procedure step 9 (and step 1): the indicator field from the stationary
  * solid and the particles at their current positions, the node owners, the
  * owner's contact angle (psi = cos(theta) phi0) and solid velocity (R-PART). */
@@ -578,7 +637,7 @@ static void particle_statics(orc_state *st)
             int own = -1;
             for (int k = 0; k < st->np; ++k) {
                 const double *q = st->pin + k * NPIN;
-                double r = hypot(per(x - q[P_X], nx), per(y - q[P_Y], ny));
+                double r = hypot(per(x - q[P_X], nx), pery(p, y - q[P_Y]));
                 double zk = r < q[P_R] + 5.0 * p->D ? 0.5 + 0.5 * tanh((q[P_R] - r) / (p->D / 2.0)) : 0.0;
                 sum += zk;
                 if (zk > best) { best = zk; own = k; c = q[P_COS]; }
@@ -591,7 +650,7 @@ static void particle_statics(orc_state *st)
             F[F_USOLY][o] = 0.0;
             if (own >= 0) { /* u_s = u_p + omega_p x (x - x_p) */
                 const double *q = st->pin + own * NPIN;
-                double rx = per(x - q[P_X], nx), ry = per(y - q[P_Y], ny);
+                double rx = per(x - q[P_X], nx), ry = pery(p, y - q[P_Y]);
                 F[F_USOLX][o] = q[P_UX] - q[P_OM] * ry;
                 F[F_USOLY][o] = q[P_UY] + q[P_OM] * rx;
             }
@@ -631,7 +690,7 @@ static void particles_update(orc_state *st)
             const double *q = st->pin + k * NPIN;
             double rho = F[F_RHO][o];
             double fx = rho * F[F_AX][o], fy = rho * F[F_AY][o]; /* rho f dt, Eq. Ff */
-            double rx = per(x - q[P_X], nx), ry = per(y - q[P_Y], ny);
+            double rx = per(x - q[P_X], nx), ry = pery(p, y - q[P_Y]);
             acc[k * 5 + 0] -= fx;
             acc[k * 5 + 1] -= fy;
             acc[k * 5 + 2] -= rx * fy - ry * fx;
@@ -654,7 +713,7 @@ static void particles_update(orc_state *st)
         for (int j = 0; j < np && p->rep_eps > 0.0; ++j) {
             if (j == k) continue;
             const double *qj = st->pin + j * NPIN;
-            repulsion(per(q[P_X] - qj[P_X], nx), per(q[P_Y] - qj[P_Y], ny), R + qj[P_R], p->rep_xi, p->rep_eps, t);
+            repulsion(per(q[P_X] - qj[P_X], nx), pery(p, q[P_Y] - qj[P_Y]), R + qj[P_R], p->rep_xi, p->rep_eps, t);
             fr[0] += t[0]; fr[1] += t[1];
         }
         const double wall[4] = {p->wall_y0, p->wall_y1, p->wall_x0, p->wall_x1};
@@ -679,7 +738,7 @@ static void particles_update(orc_state *st)
         n[P_X] = q[P_X] + q[P_UX];
         n[P_Y] = q[P_Y] + q[P_UY];
         n[P_X] -= nx * floor(n[P_X] / nx);
-        n[P_Y] -= ny * floor(n[P_Y] / ny);
+        if (!p->bounce_y) n[P_Y] -= ny * floor(n[P_Y] / ny);
         /* Eq. (Ffin), explicit: carried to the next update */
         o[Q_FINX] = rp > 0.0 ? rin * V * (n[P_UX] - q[P_UX]) : 0.0;
         o[Q_FINY] = rp > 0.0 ? rin * V * (n[P_UY] - q[P_UY]) : 0.0;
@@ -802,7 +861,10 @@ static void collide_all(orc_state *st)
     }
 }
 
-/* Streaming: f_i(x + c_i, t + 1) = f_i*(x, t), periodic. */
+/* Streaming: f_i(x + c_i, t + 1) = f_i*(x, t), periodic; with walls a
+ * population that would cross one returns to its node in the opposite
+ * direction (R-WALL). */
+static const int OPP[9] = {0, 3, 4, 1, 2, 7, 8, 5, 6};
 static void stream_all(orc_state *st)
 {
     const int nx = st->p.nx, ny = st->p.ny;
@@ -811,8 +873,14 @@ static void stream_all(orc_state *st)
         for (int y = 0; y < ny; ++y)
             for (int x = 0; x < nx; ++x) {
                 long o = (long)y * nx + x, d = nb(nx, ny, x, y, i);
-                st->g[i * N + d] = st->gpost[i * N + o];
-                st->f[i * N + d] = st->fpost[i * N + o];
+                int j = i;
+                const int yy = y + CY[i];
+                if (st->p.bounce_y && (yy < 0 || yy >= ny)) {
+                    d = o;
+                    j = OPP[i];
+                }
+                st->g[j * N + d] = st->gpost[i * N + o];
+                st->f[j * N + d] = st->fpost[i * N + o];
             }
 }
 
@@ -871,8 +939,8 @@ void orc_energy(const orc_state *st, double *EF, double *EK)
     double *const *F = st->fld;
     double *gx = malloc(N * sizeof(double)), *gy = malloc(N * sizeof(double));
     double *qx = malloc(N * sizeof(double)), *qy = malloc(N * sizeof(double));
-    orc_grad(nx, ny, F[F_PHI], gx, gy);
-    orc_grad(nx, ny, F[F_PSI], qx, qy);
+    grad_b(nx, ny, p->bounce_y, 1.0, F[F_PHI], gx, gy);
+    grad_b(nx, ny, p->bounce_y, 1.0, F[F_PSI], qx, qy);
     const double s = p->sigma, D = p->D;
     double ef = 0.0, ek = 0.0;
     for (long o = 0; o < N; ++o) {

@@ -1,0 +1,140 @@
+"""Pins of the oracle's no-flux walls (halfway bounce-back below the first and
+above the last row, mirrored ghost rows for the finite differences) against
+what the lattice and the mathematics fix: the discrete steady channel flow
+in closed form, the exact equivalence with a periodic domain of twice the
+height for states invariant along the walls, conservation of phase mass,
+the neutral (90 degree) wetting of the wall and particles that do not see
+their periodic image through a wall.
+"""
+import numpy as np
+import pytest
+
+from paper_2311_05097_amd import workloads as W
+
+
+def _channel(orc, H, mu, F, nx=3):
+    p = W.params(nx, H, mu1=mu, mu2=mu, fbx=F, bounce_y=1)
+    phi = np.ones((H, nx))
+    return p, orc.Oracle(p, phi, np.zeros_like(phi), None, None, None)
+
+
+@pytest.mark.parametrize("mu", [0.125, 0.3])
+def test_poiseuille_discrete_closed_form(orc, mu):
+    """Steady flow between bounce-back walls driven by a body force F along
+    x, one phase (rho = 1, nu = mu).  Only three x-odd combinations of the
+    populations carry u_x in an x-invariant state: a = f1 - f3, b = f5 - f6
+    and c = f8 - f7, i.e. the moments j_x = a + b + c, Pi_xy = b - c and
+    Q_xyy = b + c.  The collision keeps j_x + F, relaxes Pi_xy to 0 at the
+    shear rate s and, with the third-order rate 1, sets Q_xyy to d0 (j_x + F)
+    (its equilibrium on the d0 lattice, Sec. 4).  Streaming a, b, c to the
+    rows j, j + 1, j - 1 with b_0 = -c*_0 and c_{H-1} = -b*_{H-1} at the walls
+    gives a linear recursion whose solution is the parabola
+        u_j = F/(2 nu) (j + 1/2)(H - 1/2 - j) + F/(2 d0) - F/2 - F/(8 nu),
+    nu = d0 (1/s - 1/2): exact curvature, walls half a node outside the rows,
+    and a uniform offset that depends on nu.  Terms of order u^2 (normal
+    stresses, pressure, a small u_y) are below 1e-9 of the flow at this
+    force."""
+    H, F, d0 = 16, 1e-8, 0.4
+    p, o = _channel(orc, H, mu, F)
+    o.step(6000)
+    phi, ux, uy, P = o.read()
+    j = np.arange(H)
+    ue = F / (2 * mu) * (j + 0.5) * (H - 0.5 - j) + F / (2 * d0) - F / 2 - F / (8 * mu)
+    assert np.abs(ux - ue[:, None]).max() <= 1e-9 * ue.max()
+    assert np.abs(uy).max() <= 0.01 * ue.max() ** 2  # second order in the flow
+    # the flow is mirror symmetric about the channel centre
+    assert np.abs(ux[:, 0] - ux[::-1, 0]).max() <= 1e-12 * ue.max()
+
+
+def _layers(H, nx):
+    """x-invariant two-layer state: phase 1 below y = 7, phase 2 above, and a
+    shear flow that vanishes half a node outside the walls."""
+    y = np.arange(H)[:, None] + np.zeros((1, nx))
+    phi = np.tanh((7.0 - y) / 1.5) - np.tanh((y + 2.0 - H) / 1.5) - 1.0
+    return phi, 0.01 * np.sin(np.pi * (y + 0.5) / H)
+
+
+def test_walls_equal_a_periodic_domain_of_twice_the_height(orc):
+    """For a state that does not vary along the walls, halfway bounce-back is
+    a rotation by 180 degrees about the wall line: the populations that a
+    wall reflects are those that the rotated copy of the domain would send
+    in.  A periodic domain of height 2H holding the state and its rotated
+    copy (phi even about y = -1/2, both velocity components odd) therefore
+    runs exactly like the walled domain of height H, with two phases of
+    different density and viscosity, so that the chemical potential, the
+    mass flux S, grad rho and the force F_c = div(Su - uS)/2 all act at the
+    walls.  This pins the reflection of both populations, the ghost rows of
+    every stencil and the parity of S and u in F_c."""
+    H, nx = 24, 4
+    kw = dict(rho1=1.0, rho2=0.2, mu1=0.1, mu2=0.05, D=3.0)
+    phi, ux = _layers(H, nx)
+    pw = W.params(nx, H, bounce_y=1, **kw)
+    a = orc.Oracle(pw, phi, np.zeros_like(phi), None, ux, None)
+    phi2 = np.concatenate([phi, phi[::-1]])
+    ux2 = np.concatenate([ux, -ux[::-1]])
+    pp = W.params(nx, 2 * H, **kw)
+    b = orc.Oracle(pp, phi2, np.zeros_like(phi2), None, ux2, None)
+    a.step(400)
+    b.step(400)
+    for fa, fb in zip(a.read(), b.read()):
+        scale = max(np.abs(fb).max(), 1e-12)
+        assert np.abs(fa - fb[:H]).max() <= 1e-12 * scale
+    # the interface moved and the flow felt the walls
+    assert np.abs(a.field("phi") - phi).max() > 1e-6
+    ga, fa_ = a.pops()
+    gb, fb_ = b.pops()
+    assert np.abs(ga - gb[:, :H]).max() <= 1e-12 * np.abs(gb).max()
+    assert np.abs(fa_ - fb_[:, :H]).max() <= 1e-12 * np.abs(fb_).max()
+
+
+def test_walls_conserve_phase_mass(orc):
+    """No phase crosses a bounce-back wall: the total of phi is kept to
+    rounding with a drop on the lower wall, gravity and a shear flow."""
+    nx, ny = 48, 32
+    y, x = np.mgrid[0:ny, 0:nx].astype(float)
+    phi = np.tanh((9.0 - np.hypot(x - 20.0, y + 0.5)) / 1.5)
+    ux = 0.004 * (y + 0.5) / ny
+    p = W.params(nx, ny, bounce_y=1, rho1=1.0, rho2=0.5, gy=-1e-5, rho_ref=0.5, D=3.0)
+    o = orc.Oracle(p, phi, np.zeros_like(phi), None, ux, None)
+    m0 = o.mass()
+    o.step(300)
+    assert abs(o.mass() - m0) <= 1e-12 * np.abs(phi).sum()
+    assert np.abs(o.field("phi") - phi).max() > 1e-4
+
+
+@pytest.mark.slow
+def test_neutral_wall_keeps_a_half_disk(orc):
+    """The walls are neutral (90 degrees, no wetting term): a half disk of
+    phase 1 centred on the wall line y = -1/2 is a free-energy minimum for its
+    area, so it keeps its radius along the wall and at its apex."""
+    nx, ny, R = 64, 36, 14.0
+    y, x = np.mgrid[0:ny, 0:nx].astype(float)
+    phi = np.tanh((R - np.hypot(x - 31.5, y + 0.5)) / 2.0)
+    o = orc.Oracle(W.params(nx, ny, bounce_y=1), phi, np.zeros_like(phi), None, None, None)
+    o.step(1500)
+    f = o.field("phi")
+
+    def crossing(v):
+        k = np.nonzero((v[:-1] > 0) & (v[1:] <= 0))[0][0]
+        return k + v[k] / (v[k] - v[k + 1])
+    # column x = 31 and row y = 0 both lie half a node off the disk's axes
+    r = np.sqrt(R * R - 0.25)
+    apex = crossing(f[:, 31]) + 0.5          # height above the wall line
+    half = crossing(f[0, 31:]) - 0.5         # distance from the centre x = 31.5
+    assert abs(apex - r) < 0.1 and abs(half - r) < 0.1, (apex, half, r)
+
+
+def test_particles_see_no_image_through_the_walls(orc):
+    """With walls the particle indicator and owner use the distance in y
+    without the periodic image: a particle at the lower wall leaves the top
+    rows untouched; in the periodic domain its image reaches them."""
+    nx, ny = 40, 30
+    part = [W.particle(20.0, 3.0, 4.0, 1.0, 90.0)]
+    for walls in (1, 0):
+        p = W.params(nx, ny, bounce_y=walls)
+        o = orc.Oracle(p, np.zeros((ny, nx)), np.zeros((ny, nx)), None, None, None, particles=part)
+        top = o.field("phi0")[-2:]  # beyond the cutoff R + 5 D = 24 from y = 3
+        if walls:
+            assert np.all(top == 0.0)
+        else:
+            assert top.max() > 0.1
