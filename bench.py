@@ -350,6 +350,13 @@ def main():
         extra["C2_stable_fp32"] = {"mlups": round(e["mlups"], 1), "tile": t, "g": 0.0, "mu1": 0.3,
                                    "roofline": roofline("fp32", e["nodes"], e["kernel_ms"]),
                                    "mass_drift": e["mass_drift"], "finite": e["finite"]}
+        # the same, closed by no-flux bounce-back walls below and above (the
+        # wall variant of the step kernel)
+        s.params.update(bounce_y=1)
+        e = run_gpu(s, "fp32", args.steps, args.warmup, t)
+        extra["C2_walls_fp32"] = {"mlups": round(e["mlups"], 1), "tile": t, "bounce_y": 1,
+                                  "roofline": roofline("fp32", e["nodes"], e["kernel_ms"]),
+                                  "mass_drift": e["mass_drift"], "finite": e["finite"]}
         for st in ("fp32", "fp16dev", "fp64"):
             t = autotune.best_tile(R.params, st)
             e = run_gpu(R, st, 300, 20, t)

@@ -10,7 +10,8 @@
  * consistent Navier-Stokes flow (Sec. 3.2; viscosity mu/(1-phi0) in the
  * solid), with the Hermite-moment MRT collision of Sec. 4 and the procedure
  * of Sec. 3.3 (steps 1-6, stationary solids u_s = 0).  Domains are periodic in
- * x and y; walls are diffuse solids given through phi0.
+ * x, and in y unless bounce_y is set; other walls are diffuse solids given
+ * through phi0.
  *
  * Conventions for every function:
  *   - return value: LBM_OK (0) or a negative LBM_E* code; nothing throws
@@ -86,6 +87,13 @@ typedef struct {
                               wall repulsion (mirror image of the particle)    */
     int32_t np;            /* number of free particles, 0..1024                  */
     int32_t walls;         /* bit 0: wall_y0, 1: wall_y1, 2: wall_x0, 3: wall_x1 */
+    /* 1: no-flux walls half a node below row 0 and above row ny - 1 (the
+       no-flux condition of the channel cases of Sec. 4.2 and 4.5): halfway
+       bounce-back of g_i and f_i (no slip), ghost rows of the finite
+       differences mirrored (phi, mu, rho, phi0, psi even: a neutral 90-degree
+       wall; the mass flux S as their gradient; the velocity in F_c odd),
+       particle distances in y without the periodic image.  0: periodic. */
+    int32_t bounce_y;
 } lbm_params;
 
 typedef struct lbm_domain lbm_domain;

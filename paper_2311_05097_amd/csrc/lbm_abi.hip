@@ -103,6 +103,7 @@ int validate(const lbm_params* p) {
     for (double v : r)
         if (!std::isfinite(v)) return fail(LBM_EINVAL, "repulsion and wall parameters must be finite");
     if (p->walls < 0 || p->walls > 15) return fail(LBM_EINVAL, "walls must lie in 0..15");
+    if (p->bounce_y != 0 && p->bounce_y != 1) return fail(LBM_EINVAL, "bounce_y must be 0 or 1");
     return LBM_OK;
 }
 
@@ -242,6 +243,7 @@ void make_job(lbm_domain* d, int32_t n_active, int64_t step0, bool with_out, int
     J.n_active = n_active;
     J.tile_base = tile_base;
     J.np = d->p.np;
+    J.walls = d->p.bounce_y;
     if (d->p.np > 0) {
         J.parts = (const double*)(ws + L.off_parts);
         J.owner = (const int32_t*)(ws + L.off_owner);
@@ -263,12 +265,16 @@ template <class S, int TY, int MODE>
 int launch_tiles(lbm_domain* d, int t) {
     const Job<S>* J = (const Job<S>*)(d->ws + d->L.off_job);
     const TileEntry* T = (const TileEntry*)(d->ws + d->L.off_tiles);
-    if (MODE != MODE_INIT && d->p.np > 0)
-        hipLaunchKernelGGL((k_tile<S, TY, MODE, true>), dim3(d->L.ntiles), dim3(TileCfg<TY>::NT), 0, d->stream, J,
-                           T, d->L.ntiles, t);
+    const dim3 grid(d->L.ntiles), block(TileCfg<TY>::NT);
+    const bool part = MODE != MODE_INIT && d->p.np > 0, wall = d->p.bounce_y != 0;
+    if (part && wall)
+        hipLaunchKernelGGL((k_tile<S, TY, MODE, true, true>), grid, block, 0, d->stream, J, T, d->L.ntiles, t);
+    else if (part)
+        hipLaunchKernelGGL((k_tile<S, TY, MODE, true>), grid, block, 0, d->stream, J, T, d->L.ntiles, t);
+    else if (wall)
+        hipLaunchKernelGGL((k_tile<S, TY, MODE, false, true>), grid, block, 0, d->stream, J, T, d->L.ntiles, t);
     else
-        hipLaunchKernelGGL((k_tile<S, TY, MODE>), dim3(d->L.ntiles), dim3(TileCfg<TY>::NT), 0, d->stream, J, T,
-                           d->L.ntiles, t);
+        hipLaunchKernelGGL((k_tile<S, TY, MODE>), grid, block, 0, d->stream, J, T, d->L.ntiles, t);
     HIPCHK(hipGetLastError());
     return LBM_OK;
 }
@@ -318,7 +324,8 @@ int particle_statics(lbm_domain* d, bool all = false) {
     hipLaunchKernelGGL((k_part_static<R>), dim3((unsigned)L.pt_blocks), dim3(PT_X * PT_Y), 0, d->stream,
                        (const double*)(d->ws + L.off_parts), d->p.np, (const R*)(d->ws + L.off_base),
                        (R*)(d->ws + L.off_stat), (int32_t*)(d->ws + L.off_owner),
-                       (unsigned char*)(d->ws + L.off_touch), L.pitch, d->p.nx, d->p.ny, d->p.D);
+                       (unsigned char*)(d->ws + L.off_touch), L.pitch, d->p.nx, d->p.ny, d->p.D,
+                       d->p.bounce_y);
     HIPCHK(hipGetLastError());
     return LBM_OK;
 }
@@ -333,7 +340,7 @@ int particle_update(lbm_domain* d, double* nparts, double* nout) {
     hipLaunchKernelGGL((k_part_reduce<R>), dim3((unsigned)(p.np * PR_CH)), dim3(PR_NT), 0, d->stream,
                        (const double*)(d->ws + L.off_parts), (const int32_t*)(d->ws + L.off_owner),
                        (const R*)(d->ws + L.off_pf), (const R*)(d->ws + L.off_stat), L.pitch, p.nx, p.ny, p.D,
-                       (double*)(d->ws + L.off_pacc));
+                       p.bounce_y, (double*)(d->ws + L.off_pacc));
     HIPCHK(hipGetLastError());
     PartParams pp;
     pp.gx = p.gx;
@@ -347,6 +354,7 @@ int particle_update(lbm_domain* d, double* nparts, double* nout) {
     pp.walls = p.walls;
     pp.nx = p.nx;
     pp.ny = p.ny;
+    pp.bounce_y = p.bounce_y;
     hipLaunchKernelGGL(k_part_update, dim3(1), dim3(PU_NT), 0, d->stream, (const double*)(d->ws + L.off_parts),
                        (const double*)(d->ws + L.off_pout), (const double*)(d->ws + L.off_pacc), p.np, pp, nparts,
                        nout);
@@ -400,7 +408,8 @@ int create_impl(lbm_domain* d, const double* phi, const double* phi0, const doub
         hipLaunchKernelGGL((k_static<R>), dim3(nb), dim3(NT), 0, d->stream,
                            (const double*)(d->ws + L.off_stage), st, L.pitch, N);
         HIPCHK(hipGetLastError());
-        hipLaunchKernelGGL((k_lap_psi<R>), dim3(nb), dim3(NT), 0, d->stream, st, L.pitch, d->p.nx, d->p.ny);
+        hipLaunchKernelGGL((k_lap_psi<R>), dim3(nb), dim3(NT), 0, d->stream, st, L.pitch, d->p.nx, d->p.ny,
+                           d->p.bounce_y);
         HIPCHK(hipGetLastError());
     }
     int rc = upload_job<S>(d, 0, false);
@@ -796,11 +805,17 @@ int batch_capture(lbm_batch* b, int64_t nsteps) {
     const Job<S>* J = (const Job<S>*)(b->ws + b->off_jobs);
     const TileEntry* T = (const TileEntry*)(b->ws + b->off_tiles);
     const int nt = (int)b->tiles.size();
+    bool wall = false;  // the wall variant when any member has bounce-back walls
+    for (const lbm_domain* d : b->members) wall = wall || d->p.bounce_y != 0;
     HIPCHK(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
     hipError_t le = hipSuccess;
     for (int64_t t = 0; t < nsteps && le == hipSuccess; ++t) {
-        hipLaunchKernelGGL((k_tile<S, TY, MODE_STEP>), dim3(nt), dim3(TileCfg<TY>::NT), 0, b->stream, J, T, nt,
-                           (int)t);
+        if (wall)
+            hipLaunchKernelGGL((k_tile<S, TY, MODE_STEP, false, true>), dim3(nt), dim3(TileCfg<TY>::NT), 0,
+                               b->stream, J, T, nt, (int)t);
+        else
+            hipLaunchKernelGGL((k_tile<S, TY, MODE_STEP>), dim3(nt), dim3(TileCfg<TY>::NT), 0, b->stream, J, T,
+                               nt, (int)t);
         le = hipGetLastError();
     }
     hipError_t ce = hipStreamEndCapture(b->stream, &b->graph);  // always leave capture mode

@@ -146,6 +146,7 @@ struct Job {
     int32_t n_active;         // launches with t >= n_active leave this job alone
     int32_t tile_base;        // first tile of this job in the tile table
     int32_t np;               // free particles (0: none)
+    int32_t walls;            // no-flux bounce-back walls below row 0 and above row ny - 1
     const double* parts;      // [np][PSTRIDE] particle state (Sec. 2.4)
     const int32_t* owner;     // [pitch] owning particle of each node, -1 if none
     typename S::R* pf;        // [3][pitch] rho f dt (x, y) and rho at owned nodes
@@ -172,6 +173,22 @@ __device__ __forceinline__ double perd(double d, int n) {
 __device__ __forceinline__ int wrapi(int v, int n) {
     v %= n;
     return v < 0 ? v + n : v;
+}
+
+// Row of the node that row v (possibly outside 0..n-1) stands for: the
+// periodic image, or with walls at y = -1/2 and n - 1/2 the mirrored row
+// (-1 -> 0, -2 -> 1, n -> n - 1; rows further out, which only ragged tiles
+// taller than the domain visit, fold again and stay inside).
+__device__ __forceinline__ int rowof(int v, int n, int walls) {
+    if (!walls) return wrapi(v, n);
+    const int m = wrapi(v, 2 * n);
+    return m < n ? m : 2 * n - 1 - m;
+}
+
+// Coordinate difference along y: the nearest periodic image, or the plain
+// difference between walls.
+__device__ __forceinline__ double perdy(double d, int n, int walls) {
+    return walls ? d : perd(d, n);
 }
 
 // Map the hardware block index so that each of the 8 XCDs (blocks are dealt
@@ -267,6 +284,17 @@ __device__ __forceinline__ void hermite_inv(const Coef<R>& c, const R* m, R* f) 
 }
 
 // ------------------------------------------------------ population access
+// Plane that the population of direction i is stored in: its own, or next to
+// a wall (halfway bounce-back) the opposite one for the directions that would
+// cross it (c_y = -1 at the lower wall, +1 at the upper).
+enum { WALL_NONE = 0, WALL_S = 1, WALL_N = 2 };
+template <int WALL>
+__device__ __forceinline__ constexpr int plane(int i) {
+    constexpr int opp[9] = {0, 3, 4, 1, 2, 7, 8, 5, 6};
+    const bool down = i == 4 || i == 7 || i == 8, up = i == 2 || i == 5 || i == 6;
+    return (WALL == WALL_S && down) || (WALL == WALL_N && up) ? opp[i] : i;
+}
+
 // Node offsets are 32-bit (domains hold fewer than 2^31 nodes); each plane
 // base is a uniform pointer, so loads use a scalar base plus a 32-bit vector
 // offset.
@@ -295,12 +323,13 @@ struct AccessFull {  // FP64 / FP32: plain values
 #pragma unroll
         for (int i = 0; i < 9; ++i) f[i] = P.p[(9 + i) * pitch + o];
     }
+    template <int WALL = WALL_NONE>
     static __device__ __forceinline__ void store(const Pop& P, int64_t pitch, const uint32_t* dst,
                                                  const Coef<R>&, const R* g, const R* f, int64_t) {
 #pragma unroll
-        for (int i = 0; i < 9; ++i) P.p[i * pitch + dst[i]] = g[i];
+        for (int i = 0; i < 9; ++i) P.p[plane<WALL>(i) * pitch + dst[i]] = g[i];
 #pragma unroll
-        for (int i = 0; i < 9; ++i) P.p[(9 + i) * pitch + dst[i]] = f[i];
+        for (int i = 0; i < 9; ++i) P.p[(9 + plane<WALL>(i)) * pitch + dst[i]] = f[i];
     }
 };
 template <> struct Access<StF64> : AccessFull<StF64> {};
@@ -349,6 +378,7 @@ struct AccessHalf {  // 16-bit codes + fixed-point rest population
     }
     // mfix: the node's conserved sum_i g_i in fixed point; g_0 is written so
     // that the stored values sum to it exactly.
+    template <int WALL = WALL_NONE>
     static __device__ __forceinline__ void store(const Pop& P, int64_t pitch, const uint32_t* dst,
                                                  const Coef<float>& c, const float* g, const float* f,
                                                  int64_t mfix) {
@@ -356,12 +386,12 @@ struct AccessHalf {  // 16-bit codes + fixed-point rest population
 #pragma unroll
         for (int i = 0; i < 8; ++i) {
             const uint16_t code = Sh::enc(g[i + 1] * c.sg);
-            P.gm[i * pitch + dst[i + 1]] = code;
+            P.gm[(plane<WALL>(i + 1) - 1) * pitch + dst[i + 1]] = code;
             s += gfix(c, code);
         }
         P.g0[dst[0]] = mfix - (int64_t)s;
 #pragma unroll
-        for (int i = 0; i < 9; ++i) P.fm[i * pitch + dst[i]] = Sh::enc(f[i] * c.sf);
+        for (int i = 0; i < 9; ++i) P.fm[plane<WALL>(i) * pitch + dst[i]] = Sh::enc(f[i] * c.sf);
     }
 };
 template <> struct Access<StF16> : AccessHalf<StF16> {};
@@ -390,7 +420,9 @@ struct TileCfg {
 // barrier, so their latencies overlap.
 // PART: the domain has free particles (their branch and its LDS are compiled
 // only into this variant, so the plain kernel keeps its register budget).
-template <class S, int TY, int MODE, bool PART = false>
+// WALL: some job may have bounce-back walls (Job::walls); the plain kernel
+// carries none of their instructions.
+template <class S, int TY, int MODE, bool PART = false, bool WALL = false>
 __global__ __launch_bounds__(TileCfg<TY>::NT) void k_tile(const Job<S>* __restrict__ jobs,
                                                          const TileEntry* __restrict__ tiles, int ntiles,
                                                          int t) {
@@ -413,7 +445,7 @@ __global__ __launch_bounds__(TileCfg<TY>::NT) void k_tile(const Job<S>* __restri
     __shared__ R sSy[H1 * W1];
     __shared__ R sw[H1 * W1];
     __shared__ int s_col[W3];                     // periodic x of LDS column lx (x0 + lx - 3)
-    __shared__ int s_row[H3];                     // periodic y * nx of LDS row ly (y0 + ly - 3)
+    __shared__ int s_row[H3];                     // y * nx of LDS row ly (y0 + ly - 3), periodic or mirrored
     __shared__ double sred[NW][NPART];
     __shared__ long long sired[NW];
 
@@ -433,13 +465,15 @@ __global__ __launch_bounds__(TileCfg<TY>::NT) void k_tile(const Job<S>* __restri
     const R* __restrict__ st = J.stat;
     const int x0 = te.x0, y0 = te.y0;
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int walls = WALL ? J.walls : 0;
 
-    // periodic index tables (the only integer divisions of the kernel)
+    // index tables (the only integer divisions of the kernel); with walls a
+    // row outside the domain reads its mirror image (ghost rows)
     for (int i = tid; i < W3 + H3; i += NTH) {
         if (i < W3)
             s_col[i] = wrapi(x0 + i - 3, nx);
         else
-            s_row[i - W3] = wrapi(y0 + (i - W3) - 3, ny) * nx;
+            s_row[i - W3] = rowof(y0 + (i - W3) - 3, ny, walls) * nx;
     }
     __syncthreads();
 
@@ -510,8 +544,11 @@ __global__ __launch_bounds__(TileCfg<TY>::NT) void k_tile(const Job<S>* __restri
         if (MODE != MODE_INIT && p < H1 * W1) {
             const int ly = p / W1, lx = p - ly * W1;
             const uint32_t o = (uint32_t)(s_row[ly + 2] + s_col[lx + 2]);
-            cux[k] = hprev[pitch + o];
-            cuy[k] = hprev[2 * pitch + o];
+            // ghost rows hold the mirrored no-slip velocity: both components odd
+            const int yy = y0 + ly - 1;
+            const R sg = (walls && (yy < 0 || yy >= ny)) ? R(-1) : R(1);
+            cux[k] = sg * hprev[pitch + o];
+            cuy[k] = sg * hprev[2 * pitch + o];
         }
     }
     __syncthreads();
@@ -601,11 +638,13 @@ __global__ __launch_bounds__(TileCfg<TY>::NT) void k_tile(const Job<S>* __restri
         // density and viscosity laws (Eq. rho) on phi clamped to [-1, 1]
         const R rho = c.srho + c.drho * clamp1(ph);
         const R muv = c.smu + c.dmu * clamp1(ph);
-        // neighbours for the push (periodic)
+        // neighbours for the push (periodic; the rows next to a wall reflect
+        // what would cross it, below)
         const int xe = x + 1 == nx ? 0 : x + 1, xw = x == 0 ? nx - 1 : x - 1;
+        const bool wall_s = walls && y == 0, wall_n = walls && y == ny - 1;
         const uint32_t rc = (uint32_t)y * (uint32_t)nx;
-        const uint32_t rn = (uint32_t)(y + 1 == ny ? 0 : y + 1) * (uint32_t)nx;
-        const uint32_t rs = (uint32_t)(y == 0 ? ny - 1 : y - 1) * (uint32_t)nx;
+        const uint32_t rn = (uint32_t)(y + 1 == ny ? (wall_n ? y : 0) : y + 1) * (uint32_t)nx;
+        const uint32_t rs = (uint32_t)(y == 0 ? (wall_s ? 0 : ny - 1) : y - 1) * (uint32_t)nx;
 
         if (MODE == MODE_INIT) {
             // Procedure step 1: g = g^eq, f = f^eq at P = 0 with the given u.
@@ -654,7 +693,7 @@ __global__ __launch_bounds__(TileCfg<TY>::NT) void k_tile(const Job<S>* __restri
             own = J.owner[o];
             if (own >= 0) {
                 const double* q = J.parts + own * PSTRIDE;
-                const double rx = perd((double)x - q[PX], nx), ry = perd((double)y - q[PY], ny);
+                const double rx = perd((double)x - q[PX], nx), ry = perdy((double)y - q[PY], ny, walls);
                 usolx = (R)(q[PUX] - q[POM] * ry);
                 usoly = (R)(q[PUY] + q[POM] * rx);
                 const R cth = (R)q[PCOS];
@@ -804,20 +843,27 @@ __global__ __launch_bounds__(TileCfg<TY>::NT) void k_tile(const Job<S>* __restri
         hermite_inv(c, m, fk);
 
         // ---- push to the other copy, periodic ----
+        // Next to a wall (halfway bounce-back) the three populations that
+        // would cross it return to this node in the opposite directions.
         uint32_t dst[9];
         dst[0] = o;
         dst[1] = rc + xe;
-        dst[2] = rn + x;
+        dst[2] = wall_n ? o : rn + x;
         dst[3] = rc + xw;
-        dst[4] = rs + x;
-        dst[5] = rn + xe;
-        dst[6] = rn + xw;
-        dst[7] = rs + xw;
-        dst[8] = rs + xe;
+        dst[4] = wall_s ? o : rs + x;
+        dst[5] = wall_n ? o : rn + xe;
+        dst[6] = wall_n ? o : rn + xw;
+        dst[7] = wall_s ? o : rs + xw;
+        dst[8] = wall_s ? o : rs + xe;
         // relative rest population: g_0 - phi^n with phi^n the value written
         // to history below; (php - ph) is exact for nearby values
         if (S::kRel) gk[0] += php - ph;
-        A::store(J.pop[par ^ 1], pitch, dst, c, gk, fk, mk);
+        if (wall_s)
+            A::template store<WALL_S>(J.pop[par ^ 1], pitch, dst, c, gk, fk, mk);
+        else if (wall_n)
+            A::template store<WALL_N>(J.pop[par ^ 1], pitch, dst, c, gk, fk, mk);
+        else
+            A::store(J.pop[par ^ 1], pitch, dst, c, gk, fk, mk);
         R* hw = J.hist[par ^ 1];
         hw[o] = ph;
         hw[pitch + o] = ux;
@@ -880,16 +926,16 @@ __global__ __launch_bounds__(NT) void k_part_base(const double* __restrict__ in,
     base[pitch + o] = (R)in[2 * pitch + o];
 }
 
-// Laplacian of psi (static wetting field), periodic.
+// Laplacian of psi (static wetting field), periodic, or mirrored at walls.
 template <class R>
-__global__ __launch_bounds__(NT) void k_lap_psi(R* __restrict__ st, int64_t pitch, int nx, int ny) {
+__global__ __launch_bounds__(NT) void k_lap_psi(R* __restrict__ st, int64_t pitch, int nx, int ny, int walls) {
     const int64_t o = (int64_t)blockIdx.x * NT + threadIdx.x;
     if (o >= (int64_t)nx * ny) return;
     const int y = (int)(o / nx), x = (int)(o - (int64_t)y * nx);
     const R* psi = st + pitch;
     const int xe = x + 1 == nx ? 0 : x + 1, xw = x == 0 ? nx - 1 : x - 1;
-    const int64_t rc = (int64_t)y * nx, rn = (int64_t)(y + 1 == ny ? 0 : y + 1) * nx;
-    const int64_t rs = (int64_t)(y == 0 ? ny - 1 : y - 1) * nx;
+    const int64_t rc = (int64_t)y * nx, rn = (int64_t)rowof(y + 1, ny, walls) * nx;
+    const int64_t rs = (int64_t)rowof(y - 1, ny, walls) * nx;
     const R c4 = R(4) * psi[o];
     const R ax = (psi[rc + xe] + psi[rc + xw]) + (psi[rn + x] + psi[rs + x]);
     const R dg = (psi[rn + xe] + psi[rn + xw]) + (psi[rs + xe] + psi[rs + xw]);
@@ -912,7 +958,7 @@ __global__ __launch_bounds__(PT_NT) void k_part_static(const double* __restrict_
                                                            const R* __restrict__ base, R* __restrict__ st,
                                                            int32_t* __restrict__ owner,
                                                            unsigned char* __restrict__ touched, int64_t pitch,
-                                                           int nx, int ny, double D) {
+                                                           int nx, int ny, double D, int walls) {
     constexpr int HW = PT_X + 2, HH = PT_Y + 2;
     constexpr int NWV = PT_NT / 64;
     __shared__ int list[PT_MAXLIST];
@@ -933,7 +979,7 @@ __global__ __launch_bounds__(PT_NT) void k_part_static(const double* __restrict_
         if (k < np) {
             const double* q = parts + k * PSTRIDE;
             const double reach = q[PRAD] + PCUT * D + 1.0;  // + the halo of the Laplacian
-            const double dx = fabs(perd(cx - q[PX], nx)), dy = fabs(perd(cy - q[PY], ny));
+            const double dx = fabs(perd(cx - q[PX], nx)), dy = fabs(perdy(cy - q[PY], ny, walls));
             h = dx <= 0.5 * PT_X + reach && dy <= 0.5 * PT_Y + reach;
         }
         const unsigned long long m = __ballot(h);
@@ -955,7 +1001,7 @@ __global__ __launch_bounds__(PT_NT) void k_part_static(const double* __restrict_
     if (cnt == 0 && !was) return;  // uniform: nothing here changed
     for (int i = tid; i < HH * HW; i += PT_NT) {
         const int ly = i / HW, lx = i - ly * HW;
-        const int x = wrapi(x0 + lx - 1, nx), y = wrapi(y0 + ly - 1, ny);
+        const int x = wrapi(x0 + lx - 1, nx), y = rowof(y0 + ly - 1, ny, walls);
         const int64_t o = (int64_t)y * nx + x;
         // the indicator in the storage's arithmetic (FP64 for FP64 storage)
         R sum = base[o], best = sum, cth = base[pitch + o];
@@ -963,7 +1009,7 @@ __global__ __launch_bounds__(PT_NT) void k_part_static(const double* __restrict_
         for (int j = 0; j < cnt; ++j) {
             const int k = list[j];
             const double* q = parts + k * PSTRIDE;
-            const R dx = (R)perd(x - q[PX], nx), dy = (R)perd(y - q[PY], ny);
+            const R dx = (R)perd(x - q[PX], nx), dy = (R)perdy(y - q[PY], ny, walls);
             const R rad = (R)q[PRAD], cut = rad + (R)(PCUT * D);
             // clearly outside the support: skip the square root and tanh
             if (dx * dx + dy * dy > cut * cut * R(1.000001)) continue;
@@ -1008,17 +1054,23 @@ template <class R>
 __global__ __launch_bounds__(PR_NT) void k_part_reduce(const double* __restrict__ parts,
                                                       const int32_t* __restrict__ owner,
                                                       const R* __restrict__ pf, const R* __restrict__ st,
-                                                      int64_t pitch, int nx, int ny, double D,
+                                                      int64_t pitch, int nx, int ny, double D, int walls,
                                                       double* __restrict__ acc) {
     __shared__ double sh[PR_NT][5];
     const int k = blockIdx.x / PR_CH, band = blockIdx.x % PR_CH, tid = threadIdx.x;
     const double* q = parts + k * PSTRIDE;
     const double reach = q[PRAD] + PCUT * D;
-    const int xl = (int)ceil(q[PX] - reach), yl = (int)ceil(q[PY] - reach);
+    const int xl = (int)ceil(q[PX] - reach);
+    int yl = (int)ceil(q[PY] - reach);
     int w = (int)floor(q[PX] + reach) - xl + 1, h = (int)floor(q[PY] + reach) - yl + 1;
+    if (walls) {  // no image in y: the box is cut at the walls
+        const int yh = yl + h - 1 < ny - 1 ? yl + h - 1 : ny - 1;
+        yl = yl > 0 ? yl : 0;
+        h = yh >= yl ? yh - yl + 1 : 0;
+    }
     // a box narrower than the domain holds each node once, and there the plain
     // difference is the nearest periodic image
-    const bool wrap_x = w >= nx, wrap_y = h >= ny;
+    const bool wrap_x = w >= nx, wrap_y = !walls && h >= ny;
     w = wrap_x ? nx : w;
     h = wrap_y ? ny : h;
     const int r0 = band * h / PR_CH, r1 = (band + 1) * h / PR_CH;
@@ -1066,6 +1118,7 @@ struct PartParams {
     double wall[4];                      // wall planes y0, y1, x0, x1
     int walls;                           // bit w: wall[w] present
     int nx, ny;
+    int bounce_y;                        // bounce-back walls: no periodic image in y
 };
 
 // Procedure steps 8 and 10: Eq. (particle) by explicit Euler (dt = 1, every
@@ -1102,8 +1155,8 @@ __global__ __launch_bounds__(PU_NT) void k_part_update(const double* parts, cons
                 // far pairs (no image within the threshold) contribute nothing
                 const double lim = R + qj[PRAD] + pp.xi;
                 const double ax = fabs(q[PX] - qj[PX]), ay = fabs(q[PY] - qj[PY]);
-                if ((ax > lim && pp.nx - ax > lim) || (ay > lim && pp.ny - ay > lim)) continue;
-                const double dx = perd(q[PX] - qj[PX], pp.nx), dy = perd(q[PY] - qj[PY], pp.ny);
+                if ((ax > lim && pp.nx - ax > lim) || (ay > lim && (pp.bounce_y || pp.ny - ay > lim))) continue;
+                const double dx = perd(q[PX] - qj[PX], pp.nx), dy = perdy(q[PY] - qj[PY], pp.ny, pp.bounce_y);
                 const double m = rep_scale(hypot(dx, dy), R + qj[PRAD], pp.xi, pp.eps);
                 sx += m * dx;
                 sy += m * dy;
@@ -1152,7 +1205,7 @@ __global__ __launch_bounds__(PU_NT) void k_part_update(const double* parts, cons
         n[PX] = q[PX] + q[PUX];
         n[PY] = q[PY] + q[PUY];
         n[PX] -= pp.nx * floor(n[PX] / pp.nx);
-        n[PY] -= pp.ny * floor(n[PY] / pp.ny);
+        if (!pp.bounce_y) n[PY] -= pp.ny * floor(n[PY] / pp.ny);
         o7[QFX] = a[0];
         o7[QFY] = a[1];
         o7[QT] = a[2];

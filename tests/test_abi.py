@@ -71,6 +71,10 @@ def test_workspace_size_and_validation_host_only():
         lbmgls.workspace_bytes(dict(w.params, nx=4), "fp32")
     with pytest.raises(lbmgls.LbmError):
         lbmgls.workspace_bytes(dict(w.params, d0=1.2), "fp32")
+    # walls change no buffer; any value but 0 and 1 is rejected
+    assert lbmgls.workspace_bytes(dict(w.params, bounce_y=1), "fp32") == n32
+    with pytest.raises(lbmgls.LbmError):
+        lbmgls.workspace_bytes(dict(w.params, bounce_y=2), "fp32")
 
 
 def test_binding_shares_torchs_hip_runtime():
