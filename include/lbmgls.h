@@ -10,8 +10,8 @@
  * consistent Navier-Stokes flow (Sec. 3.2; viscosity mu/(1-phi0) in the
  * solid), with the Hermite-moment MRT collision of Sec. 4 and the procedure
  * of Sec. 3.3 (steps 1-6, stationary solids u_s = 0).  Domains are periodic in
- * x, and in y unless bounce_y is set; other walls are diffuse solids given
- * through phi0.
+ * x unless bounce_x is set and in y unless bounce_y is set; other walls are
+ * diffuse solids given through phi0.
  *
  * Conventions for every function:
  *   - return value: LBM_OK (0) or a negative LBM_E* code; nothing throws
@@ -94,6 +94,10 @@ typedef struct {
        wall; the mass flux S as their gradient; the velocity in F_c odd),
        particle distances in y without the periodic image.  0: periodic. */
     int32_t bounce_y;
+    /* the same left of column 0 and right of column nx - 1 (the side walls of
+       the channel of Sec. 4.5); at a corner a population that would leave
+       through either wall returns to its node. */
+    int32_t bounce_x;
 } lbm_params;
 
 typedef struct lbm_domain lbm_domain;

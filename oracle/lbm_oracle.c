@@ -77,16 +77,18 @@
  *              nearest periodic image, particle-wall against optional
  *              axis-aligned wall planes (mirror image of the particle);
  *              none when the stiffness parameter is <= 0.
- *   R-WALL   with bounce_y set, no-flux walls halfway outside the first and
- *            last rows (y = -1/2 and ny - 1/2): populations that would
- *            cross a wall are reflected into the opposite direction at the
- *            same node (halfway bounce-back, neutral wetting); the
- *            finite-difference stencils read mirrored ghost rows (-1 -> 0,
- *            -2 -> 1, ...): scalars unchanged, the mass flux S as the
- *            gradient of such a scalar (S_y changes sign) and the lagged
- *            velocity in T of F_c odd in both components (no slip); free
- *            particles measure distances in y without the periodic image.
- *   Periodic in x, and in y unless bounce_y is set.
+ *   R-WALL   with bounce_y (bounce_x) set, no-flux walls half a node
+ *            outside the first and last rows (columns): populations that
+ *            would cross a wall return to their node in the opposite
+ *            direction (halfway bounce-back, no slip); the finite-difference
+ *            stencils read ghost nodes mirrored about the wall (-1 -> 0,
+ *            -2 -> 1, ...): scalars unchanged (a neutral 90-degree wall), the
+ *            mass flux S as the gradient of such a scalar (its normal
+ *            component changes sign) and the lagged velocity in T of F_c odd
+ *            in both components (no slip), each mirror applied in turn at a
+ *            corner; free particles measure distances across a walled
+ *            direction without the periodic image.
+ *   Periodic in every direction without walls.
  */
 #include <math.h>
 #include <omp.h>
@@ -111,6 +113,7 @@ typedef struct {
     double wall_x0, wall_x1, wall_y0, wall_y1; /* wall planes for the repulsion  */
     int32_t walls;               /* bit 0: y0, 1: y1, 2: x0, 3: x1 present  */
     int32_t bounce_y;            /* R-WALL: no-flux walls below and above   */
+    int32_t bounce_x;            /* R-WALL: no-flux walls left and right    */
 } orc_params;
 
 /* One free rigid disk (Sec. 2.4): centre, translational and angular velocity,
@@ -316,29 +319,31 @@ static inline long nb(int nx, int ny, int x, int y, int i)
     return (long)yy * nx + xx;
 }
 
-/* Neighbour value in direction i: periodic, or with walls (R-WALL) the
- * mirrored ghost row times the field's parity under the reflection. */
-static inline double nbv(const double *chi, int nx, int ny, int walls, double parity, int x, int y, int i)
+/* Index along one direction of a node that v (at most one node outside
+ * 0..n-1) stands for: the periodic image, or with walls (R-WALL) the mirror
+ * image; *ghost tells which. */
+static inline int img(int v, int n, int walls, int *ghost)
 {
-    int xx = ((x + CX[i]) % nx + nx) % nx;
-    int yy = y + CY[i];
-    double sg = 1.0;
-    if (walls && (yy < 0 || yy >= ny)) {
-        yy = yy < 0 ? -1 - yy : 2 * ny - 1 - yy;
-        sg = parity;
-    } else {
-        yy = (yy % ny + ny) % ny;
-    }
-    return sg * chi[(long)yy * nx + xx];
+    *ghost = walls && (v < 0 || v >= n);
+    if (*ghost) return v < 0 ? -1 - v : 2 * n - 1 - v;
+    return (v % n + n) % n;
 }
 
-static void grad_b(int nx, int ny, int walls, double parity, const double *chi, double *gx, double *gy)
+/* Neighbour value of a scalar in direction i (even under every mirror). */
+static inline double nbv(const double *chi, int nx, int ny, int wx, int wy, int x, int y, int i)
+{
+    int gx, gy;
+    const int xx = img(x + CX[i], nx, wx, &gx), yy = img(y + CY[i], ny, wy, &gy);
+    return chi[(long)yy * nx + xx];
+}
+
+static void grad_b(int nx, int ny, int wx, int wy, const double *chi, double *gx, double *gy)
 {
     for (int y = 0; y < ny; ++y)
         for (int x = 0; x < nx; ++x) {
             double sx = 0.0, sy = 0.0;
             for (int i = 0; i < 9; ++i) {
-                double v = nbv(chi, nx, ny, walls, parity, x, y, i);
+                double v = nbv(chi, nx, ny, wx, wy, x, y, i);
                 sx += WT[i] * CX[i] * v;
                 sy += WT[i] * CY[i] * v;
             }
@@ -347,25 +352,25 @@ static void grad_b(int nx, int ny, int walls, double parity, const double *chi, 
         }
 }
 
-static void lap_b(int nx, int ny, int walls, const double *chi, double *lap)
+static void lap_b(int nx, int ny, int wx, int wy, const double *chi, double *lap)
 {
     for (int y = 0; y < ny; ++y)
         for (int x = 0; x < nx; ++x) {
             long o = (long)y * nx + x;
             double s = 0.0;
-            for (int i = 0; i < 9; ++i) s += WT[i] * (nbv(chi, nx, ny, walls, 1.0, x, y, i) - chi[o]);
+            for (int i = 0; i < 9; ++i) s += WT[i] * (nbv(chi, nx, ny, wx, wy, x, y, i) - chi[o]);
             lap[o] = 6.0 * s; /* 2 / c_s^2 with c_s^2 = 1/3 */
         }
 }
 
 void orc_grad(int nx, int ny, const double *chi, double *gx, double *gy)
 {
-    grad_b(nx, ny, 0, 1.0, chi, gx, gy);
+    grad_b(nx, ny, 0, 0, chi, gx, gy);
 }
 
 void orc_lap(int nx, int ny, const double *chi, double *lap)
 {
-    lap_b(nx, ny, 0, chi, lap);
+    lap_b(nx, ny, 0, 0, chi, lap);
 }
 
 /* ---- Eq. (potential): chemical potential, wetting terms through psi ---- */
@@ -375,8 +380,8 @@ void orc_mu(const orc_params *p, const double *phi, const double *phi0, const do
     const int nx = p->nx, ny = p->ny;
     const long N = (long)nx * ny;
     double *lphi = malloc(N * sizeof(double)), *lpsi = malloc(N * sizeof(double));
-    lap_b(nx, ny, p->bounce_y, phi, lphi);
-    lap_b(nx, ny, p->bounce_y, psi, lpsi);
+    lap_b(nx, ny, p->bounce_x, p->bounce_y, phi, lphi);
+    lap_b(nx, ny, p->bounce_x, p->bounce_y, psi, lpsi);
     const double s = p->sigma, D = p->D;
     for (long o = 0; o < N; ++o) {
         double f = phi[o], z = phi0[o], q = psi[o];
@@ -491,24 +496,20 @@ void orc_macro_node(const orc_params *p, int init, const double f[9], double rho
 /* Procedure steps 3-6 at the current time from phi (already in the state),
  * the flow distributions and the lagged velocity.  If init != 0, u* is the
  * given velocity and P = 0 (R-INIT). */
-/* T_alpha,beta = (S_alpha u_beta - u_alpha S_beta)/2 of R-FC at node (x, y),
- * periodic in x.  Rows outside the domain are periodic images, or with walls
- * (R-WALL) ghost rows built from the mirrored node: S is the gradient of a
- * scalar mirrored evenly (S_x even, S_y odd) and the no-slip velocity is odd
- * in both components. */
+/* T_alpha,beta = (S_alpha u_beta - u_alpha S_beta)/2 of R-FC at node (x, y).
+ * Nodes outside the domain are periodic images, or with walls (R-WALL) ghost
+ * nodes built from the mirrored node: S is the gradient of a scalar mirrored
+ * evenly (its component normal to the wall changes sign) and the no-slip
+ * velocity is odd in both components; at a corner both mirrors apply. */
 static double t_ab(const orc_state *st, int a, int b, int x, int y)
 {
-    const int nx = st->p.nx, ny = st->p.ny;
     double sS[2] = {1.0, 1.0}, sU[2] = {1.0, 1.0};
-    x = (x % nx + nx) % nx;
-    if (st->p.bounce_y && (y < 0 || y >= ny)) {
-        y = y < 0 ? -1 - y : 2 * ny - 1 - y;
-        sS[1] = -1.0;
-        sU[0] = sU[1] = -1.0;
-    } else {
-        y = (y % ny + ny) % ny;
-    }
-    const long o = (long)y * nx + x;
+    int gx, gy;
+    x = img(x, st->p.nx, st->p.bounce_x, &gx);
+    y = img(y, st->p.ny, st->p.bounce_y, &gy);
+    if (gx) { sS[0] = -sS[0]; sU[0] = -sU[0]; sU[1] = -sU[1]; }
+    if (gy) { sS[1] = -sS[1]; sU[0] = -sU[0]; sU[1] = -sU[1]; }
+    const long o = (long)y * st->p.nx + x;
     double *const *F = st->fld;
     const double S[2] = {sS[0] * F[F_SX][o], sS[1] * F[F_SY][o]};
     const double u[2] = {sU[0] * F[F_ULX][o], sU[1] * F[F_ULY][o]};
@@ -530,11 +531,11 @@ static void macro(orc_state *st, int init)
     }
     /* chemical potential, gradients, consistent mass flux S = M grad(mu)(rho1-rho2)/2 */
     orc_mu(p, F[F_PHI], F[F_PHI0], F[F_PSI], F[F_MU]);
-    const int W = p->bounce_y;
-    grad_b(nx, ny, W, 1.0, F[F_PHI], F[F_DPHIX], F[F_DPHIY]);
-    grad_b(nx, ny, W, 1.0, F[F_RHO], F[F_DRHOX], F[F_DRHOY]);
+    const int WX = p->bounce_x, WY = p->bounce_y;
+    grad_b(nx, ny, WX, WY, F[F_PHI], F[F_DPHIX], F[F_DPHIY]);
+    grad_b(nx, ny, WX, WY, F[F_RHO], F[F_DRHOX], F[F_DRHOY]);
     double *gmx = malloc(N * sizeof(double)), *gmy = malloc(N * sizeof(double));
-    grad_b(nx, ny, W, 1.0, F[F_MU], gmx, gmy);
+    grad_b(nx, ny, WX, WY, F[F_MU], gmx, gmy);
     for (long o = 0; o < N; ++o) {
         F[F_SX][o] = p->M * gmx[o] * (p->rho1 - p->rho2) / 2.0;
         F[F_SY][o] = p->M * gmy[o] * (p->rho1 - p->rho2) / 2.0;
@@ -554,8 +555,8 @@ static void macro(orc_state *st, int init)
     /* mu_phi0 (Eq. muPhi0) where a free particle owns the node (R-PART) */
     double *gzx = malloc(N * sizeof(double)), *gzy = malloc(N * sizeof(double));
     double *lphi = malloc(N * sizeof(double));
-    grad_b(nx, ny, W, 1.0, F[F_PHI0], gzx, gzy);
-    lap_b(nx, ny, W, F[F_PHI], lphi);
+    grad_b(nx, ny, WX, WY, F[F_PHI0], gzx, gzy);
+    lap_b(nx, ny, WX, WY, F[F_PHI], lphi);
     for (long o = 0; o < N; ++o) {
         F[F_MUZ][o] = 0.0;
         int k = (int)F[F_OWN][o];
@@ -616,7 +617,11 @@ static double per(double d, int n)
     return d - n * floor(d / n + 0.5);
 }
 
-/* The same in y, which is not periodic between walls (R-WALL). */
+/* The same along x and y, where a walled direction has no image (R-WALL). */
+static double perx(const orc_params *p, double d)
+{
+    return p->bounce_x ? d : per(d, p->nx);
+}
 static double pery(const orc_params *p, double d)
 {
     return p->bounce_y ? d : per(d, p->ny);
@@ -637,7 +642,7 @@ static void particle_statics(orc_state *st)
             int own = -1;
             for (int k = 0; k < st->np; ++k) {
                 const double *q = st->pin + k * NPIN;
-                double r = hypot(per(x - q[P_X], nx), pery(p, y - q[P_Y]));
+                double r = hypot(perx(p, x - q[P_X]), pery(p, y - q[P_Y]));
                 double zk = r < q[P_R] + 5.0 * p->D ? 0.5 + 0.5 * tanh((q[P_R] - r) / (p->D / 2.0)) : 0.0;
                 sum += zk;
                 if (zk > best) { best = zk; own = k; c = q[P_COS]; }
@@ -650,7 +655,7 @@ static void particle_statics(orc_state *st)
             F[F_USOLY][o] = 0.0;
             if (own >= 0) { /* u_s = u_p + omega_p x (x - x_p) */
                 const double *q = st->pin + own * NPIN;
-                double rx = per(x - q[P_X], nx), ry = pery(p, y - q[P_Y]);
+                double rx = perx(p, x - q[P_X]), ry = pery(p, y - q[P_Y]);
                 F[F_USOLX][o] = q[P_UX] - q[P_OM] * ry;
                 F[F_USOLY][o] = q[P_UY] + q[P_OM] * rx;
             }
@@ -690,7 +695,7 @@ static void particles_update(orc_state *st)
             const double *q = st->pin + k * NPIN;
             double rho = F[F_RHO][o];
             double fx = rho * F[F_AX][o], fy = rho * F[F_AY][o]; /* rho f dt, Eq. Ff */
-            double rx = per(x - q[P_X], nx), ry = pery(p, y - q[P_Y]);
+            double rx = perx(p, x - q[P_X]), ry = pery(p, y - q[P_Y]);
             acc[k * 5 + 0] -= fx;
             acc[k * 5 + 1] -= fy;
             acc[k * 5 + 2] -= rx * fy - ry * fx;
@@ -713,7 +718,7 @@ static void particles_update(orc_state *st)
         for (int j = 0; j < np && p->rep_eps > 0.0; ++j) {
             if (j == k) continue;
             const double *qj = st->pin + j * NPIN;
-            repulsion(per(q[P_X] - qj[P_X], nx), pery(p, q[P_Y] - qj[P_Y]), R + qj[P_R], p->rep_xi, p->rep_eps, t);
+            repulsion(perx(p, q[P_X] - qj[P_X]), pery(p, q[P_Y] - qj[P_Y]), R + qj[P_R], p->rep_xi, p->rep_eps, t);
             fr[0] += t[0]; fr[1] += t[1];
         }
         const double wall[4] = {p->wall_y0, p->wall_y1, p->wall_x0, p->wall_x1};
@@ -737,7 +742,7 @@ static void particles_update(orc_state *st)
         }
         n[P_X] = q[P_X] + q[P_UX];
         n[P_Y] = q[P_Y] + q[P_UY];
-        n[P_X] -= nx * floor(n[P_X] / nx);
+        if (!p->bounce_x) n[P_X] -= nx * floor(n[P_X] / nx);
         if (!p->bounce_y) n[P_Y] -= ny * floor(n[P_Y] / ny);
         /* Eq. (Ffin), explicit: carried to the next update */
         o[Q_FINX] = rp > 0.0 ? rin * V * (n[P_UX] - q[P_UX]) : 0.0;
@@ -874,8 +879,8 @@ static void stream_all(orc_state *st)
             for (int x = 0; x < nx; ++x) {
                 long o = (long)y * nx + x, d = nb(nx, ny, x, y, i);
                 int j = i;
-                const int yy = y + CY[i];
-                if (st->p.bounce_y && (yy < 0 || yy >= ny)) {
+                const int xx = x + CX[i], yy = y + CY[i];
+                if ((st->p.bounce_y && (yy < 0 || yy >= ny)) || (st->p.bounce_x && (xx < 0 || xx >= nx))) {
                     d = o;
                     j = OPP[i];
                 }
@@ -939,8 +944,8 @@ void orc_energy(const orc_state *st, double *EF, double *EK)
     double *const *F = st->fld;
     double *gx = malloc(N * sizeof(double)), *gy = malloc(N * sizeof(double));
     double *qx = malloc(N * sizeof(double)), *qy = malloc(N * sizeof(double));
-    grad_b(nx, ny, p->bounce_y, 1.0, F[F_PHI], gx, gy);
-    grad_b(nx, ny, p->bounce_y, 1.0, F[F_PSI], qx, qy);
+    grad_b(nx, ny, p->bounce_x, p->bounce_y, F[F_PHI], gx, gy);
+    grad_b(nx, ny, p->bounce_x, p->bounce_y, F[F_PSI], qx, qy);
     const double s = p->sigma, D = p->D;
     double ef = 0.0, ek = 0.0;
     for (long o = 0; o < N; ++o) {

@@ -49,12 +49,14 @@ class OrcParams(ctypes.Structure):
         ("wall_x0", ctypes.c_double), ("wall_x1", ctypes.c_double),
         ("wall_y0", ctypes.c_double), ("wall_y1", ctypes.c_double),
         ("walls", ctypes.c_int32), ("bounce_y", ctypes.c_int32),
+        ("bounce_x", ctypes.c_int32),
     ]
 
 
 # parameters of the free-particle extension; absent keys take these values
 OPTIONAL = {"rep_xi": 0.0, "rep_eps": 1.0, "wall_x0": 0.0, "wall_x1": 0.0, "wall_y0": 0.0,
-            "wall_y1": 0.0, "walls": 0, "bounce_y": 0}
+            "wall_y1": 0.0, "walls": 0, "bounce_y": 0,
+            "bounce_x": 0}
 # particle state columns (input) and per-particle outputs of the last update
 PARTICLE_IN = ["x", "y", "ux", "uy", "omega", "R", "rho_p", "cos_theta"]
 PARTICLE_OUT = ["Fx", "Fy", "T", "Fin_x", "Fin_y", "Tin", "rho_in"]

@@ -74,6 +74,9 @@ int pick_ty(const lbm_params& p) {
 
 bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
 
+// Job::walls of a domain: bit 0 walls in y, bit 1 walls in x.
+int wall_bits(const lbm_params& p) { return (p.bounce_y ? 1 : 0) | (p.bounce_x ? 2 : 0); }
+
 int validate(const lbm_params* p) {
     if (!p) return fail(LBM_EINVAL, "params is NULL");
     if (p->nx < 8 || p->ny < 8) return fail(LBM_EINVAL, "nx and ny must be >= 8");
@@ -104,6 +107,7 @@ int validate(const lbm_params* p) {
         if (!std::isfinite(v)) return fail(LBM_EINVAL, "repulsion and wall parameters must be finite");
     if (p->walls < 0 || p->walls > 15) return fail(LBM_EINVAL, "walls must lie in 0..15");
     if (p->bounce_y != 0 && p->bounce_y != 1) return fail(LBM_EINVAL, "bounce_y must be 0 or 1");
+    if (p->bounce_x != 0 && p->bounce_x != 1) return fail(LBM_EINVAL, "bounce_x must be 0 or 1");
     return LBM_OK;
 }
 
@@ -243,7 +247,7 @@ void make_job(lbm_domain* d, int32_t n_active, int64_t step0, bool with_out, int
     J.n_active = n_active;
     J.tile_base = tile_base;
     J.np = d->p.np;
-    J.walls = d->p.bounce_y;
+    J.walls = wall_bits(d->p);
     if (d->p.np > 0) {
         J.parts = (const double*)(ws + L.off_parts);
         J.owner = (const int32_t*)(ws + L.off_owner);
@@ -266,7 +270,7 @@ int launch_tiles(lbm_domain* d, int t) {
     const Job<S>* J = (const Job<S>*)(d->ws + d->L.off_job);
     const TileEntry* T = (const TileEntry*)(d->ws + d->L.off_tiles);
     const dim3 grid(d->L.ntiles), block(TileCfg<TY>::NT);
-    const bool part = MODE != MODE_INIT && d->p.np > 0, wall = d->p.bounce_y != 0;
+    const bool part = MODE != MODE_INIT && d->p.np > 0, wall = wall_bits(d->p) != 0;
     if (part && wall)
         hipLaunchKernelGGL((k_tile<S, TY, MODE, true, true>), grid, block, 0, d->stream, J, T, d->L.ntiles, t);
     else if (part)
@@ -325,7 +329,7 @@ int particle_statics(lbm_domain* d, bool all = false) {
                        (const double*)(d->ws + L.off_parts), d->p.np, (const R*)(d->ws + L.off_base),
                        (R*)(d->ws + L.off_stat), (int32_t*)(d->ws + L.off_owner),
                        (unsigned char*)(d->ws + L.off_touch), L.pitch, d->p.nx, d->p.ny, d->p.D,
-                       d->p.bounce_y);
+                       wall_bits(d->p));
     HIPCHK(hipGetLastError());
     return LBM_OK;
 }
@@ -340,7 +344,7 @@ int particle_update(lbm_domain* d, double* nparts, double* nout) {
     hipLaunchKernelGGL((k_part_reduce<R>), dim3((unsigned)(p.np * PR_CH)), dim3(PR_NT), 0, d->stream,
                        (const double*)(d->ws + L.off_parts), (const int32_t*)(d->ws + L.off_owner),
                        (const R*)(d->ws + L.off_pf), (const R*)(d->ws + L.off_stat), L.pitch, p.nx, p.ny, p.D,
-                       p.bounce_y, (double*)(d->ws + L.off_pacc));
+                       wall_bits(p), (double*)(d->ws + L.off_pacc));
     HIPCHK(hipGetLastError());
     PartParams pp;
     pp.gx = p.gx;
@@ -354,6 +358,7 @@ int particle_update(lbm_domain* d, double* nparts, double* nout) {
     pp.walls = p.walls;
     pp.nx = p.nx;
     pp.ny = p.ny;
+    pp.bounce_x = p.bounce_x;
     pp.bounce_y = p.bounce_y;
     hipLaunchKernelGGL(k_part_update, dim3(1), dim3(PU_NT), 0, d->stream, (const double*)(d->ws + L.off_parts),
                        (const double*)(d->ws + L.off_pout), (const double*)(d->ws + L.off_pacc), p.np, pp, nparts,
@@ -409,7 +414,7 @@ int create_impl(lbm_domain* d, const double* phi, const double* phi0, const doub
                            (const double*)(d->ws + L.off_stage), st, L.pitch, N);
         HIPCHK(hipGetLastError());
         hipLaunchKernelGGL((k_lap_psi<R>), dim3(nb), dim3(NT), 0, d->stream, st, L.pitch, d->p.nx, d->p.ny,
-                           d->p.bounce_y);
+                           wall_bits(d->p));
         HIPCHK(hipGetLastError());
     }
     int rc = upload_job<S>(d, 0, false);
@@ -806,7 +811,7 @@ int batch_capture(lbm_batch* b, int64_t nsteps) {
     const TileEntry* T = (const TileEntry*)(b->ws + b->off_tiles);
     const int nt = (int)b->tiles.size();
     bool wall = false;  // the wall variant when any member has bounce-back walls
-    for (const lbm_domain* d : b->members) wall = wall || d->p.bounce_y != 0;
+    for (const lbm_domain* d : b->members) wall = wall || wall_bits(d->p) != 0;
     HIPCHK(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
     hipError_t le = hipSuccess;
     for (int64_t t = 0; t < nsteps && le == hipSuccess; ++t) {

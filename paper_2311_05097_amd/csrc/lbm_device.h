@@ -146,7 +146,8 @@ struct Job {
     int32_t n_active;         // launches with t >= n_active leave this job alone
     int32_t tile_base;        // first tile of this job in the tile table
     int32_t np;               // free particles (0: none)
-    int32_t walls;            // no-flux bounce-back walls below row 0 and above row ny - 1
+    int32_t walls;            // no-flux bounce-back walls: bit 0 below row 0 and above row
+                              // ny - 1, bit 1 left of column 0 and right of column nx - 1
     const double* parts;      // [np][PSTRIDE] particle state (Sec. 2.4)
     const int32_t* owner;     // [pitch] owning particle of each node, -1 if none
     typename S::R* pf;        // [3][pitch] rho f dt (x, y) and rho at owned nodes
@@ -175,20 +176,20 @@ __device__ __forceinline__ int wrapi(int v, int n) {
     return v < 0 ? v + n : v;
 }
 
-// Row of the node that row v (possibly outside 0..n-1) stands for: the
-// periodic image, or with walls at y = -1/2 and n - 1/2 the mirrored row
+// Row (column) of the node that row v, possibly outside 0..n-1, stands for:
+// the periodic image, or with walls at -1/2 and n - 1/2 the mirrored one
 // (-1 -> 0, -2 -> 1, n -> n - 1; rows further out, which only ragged tiles
-// taller than the domain visit, fold again and stay inside).
-__device__ __forceinline__ int rowof(int v, int n, int walls) {
-    if (!walls) return wrapi(v, n);
+// larger than the domain visit, fold again and stay inside).
+__device__ __forceinline__ int imgof(int v, int n, int walled) {
+    if (!walled) return wrapi(v, n);
     const int m = wrapi(v, 2 * n);
     return m < n ? m : 2 * n - 1 - m;
 }
 
-// Coordinate difference along y: the nearest periodic image, or the plain
-// difference between walls.
-__device__ __forceinline__ double perdy(double d, int n, int walls) {
-    return walls ? d : perd(d, n);
+// Coordinate difference along a direction: the nearest periodic image, or the
+// plain difference between walls.
+__device__ __forceinline__ double perdw(double d, int n, int walled) {
+    return walled ? d : perd(d, n);
 }
 
 // Map the hardware block index so that each of the 8 XCDs (blocks are dealt
@@ -284,15 +285,17 @@ __device__ __forceinline__ void hermite_inv(const Coef<R>& c, const R* m, R* f) 
 }
 
 // ------------------------------------------------------ population access
-// Plane that the population of direction i is stored in: its own, or next to
-// a wall (halfway bounce-back) the opposite one for the directions that would
-// cross it (c_y = -1 at the lower wall, +1 at the upper).
-enum { WALL_NONE = 0, WALL_S = 1, WALL_N = 2 };
-template <int WALL>
-__device__ __forceinline__ constexpr int plane(int i) {
+// Halfway bounce-back at a node next to walls (bb: bit 0 wall below, 1 above,
+// 2 left, 3 right): a direction that would cross one of them is stored into
+// the opposite direction's plane at the node itself.
+__device__ __forceinline__ constexpr bool crosses(int i, int bb) {
+    constexpr int cx[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1}, cy[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
+    return (cy[i] < 0 && (bb & 1)) || (cy[i] > 0 && (bb & 2)) || (cx[i] < 0 && (bb & 4)) ||
+           (cx[i] > 0 && (bb & 8));
+}
+__device__ __forceinline__ constexpr int opposite(int i) {
     constexpr int opp[9] = {0, 3, 4, 1, 2, 7, 8, 5, 6};
-    const bool down = i == 4 || i == 7 || i == 8, up = i == 2 || i == 5 || i == 6;
-    return (WALL == WALL_S && down) || (WALL == WALL_N && up) ? opp[i] : i;
+    return opp[i];
 }
 
 // Node offsets are 32-bit (domains hold fewer than 2^31 nodes); each plane
@@ -323,13 +326,25 @@ struct AccessFull {  // FP64 / FP32: plain values
 #pragma unroll
         for (int i = 0; i < 9; ++i) f[i] = P.p[(9 + i) * pitch + o];
     }
-    template <int WALL = WALL_NONE>
     static __device__ __forceinline__ void store(const Pop& P, int64_t pitch, const uint32_t* dst,
                                                  const Coef<R>&, const R* g, const R* f, int64_t) {
 #pragma unroll
-        for (int i = 0; i < 9; ++i) P.p[plane<WALL>(i) * pitch + dst[i]] = g[i];
+        for (int i = 0; i < 9; ++i) P.p[i * pitch + dst[i]] = g[i];
 #pragma unroll
-        for (int i = 0; i < 9; ++i) P.p[(9 + plane<WALL>(i)) * pitch + dst[i]] = f[i];
+        for (int i = 0; i < 9; ++i) P.p[(9 + i) * pitch + dst[i]] = f[i];
+    }
+    // next to walls: the crossing directions go to the opposite planes at o
+    static __device__ __forceinline__ void store_bb(const Pop& P, int64_t pitch, const uint32_t* dst,
+                                                    uint32_t o, int bb, const Coef<R>&, const R* g, const R* f,
+                                                    int64_t) {
+#pragma unroll
+        for (int i = 0; i < 9; ++i) {
+            const bool cr = crosses(i, bb);
+            const int64_t pl = cr ? opposite(i) : i;
+            const uint32_t d = cr ? o : dst[i];
+            P.p[pl * pitch + d] = g[i];
+            P.p[(9 + pl) * pitch + d] = f[i];
+        }
     }
 };
 template <> struct Access<StF64> : AccessFull<StF64> {};
@@ -378,7 +393,6 @@ struct AccessHalf {  // 16-bit codes + fixed-point rest population
     }
     // mfix: the node's conserved sum_i g_i in fixed point; g_0 is written so
     // that the stored values sum to it exactly.
-    template <int WALL = WALL_NONE>
     static __device__ __forceinline__ void store(const Pop& P, int64_t pitch, const uint32_t* dst,
                                                  const Coef<float>& c, const float* g, const float* f,
                                                  int64_t mfix) {
@@ -386,12 +400,34 @@ struct AccessHalf {  // 16-bit codes + fixed-point rest population
 #pragma unroll
         for (int i = 0; i < 8; ++i) {
             const uint16_t code = Sh::enc(g[i + 1] * c.sg);
-            P.gm[(plane<WALL>(i + 1) - 1) * pitch + dst[i + 1]] = code;
+            P.gm[i * pitch + dst[i + 1]] = code;
             s += gfix(c, code);
         }
         P.g0[dst[0]] = mfix - (int64_t)s;
 #pragma unroll
-        for (int i = 0; i < 9; ++i) P.fm[plane<WALL>(i) * pitch + dst[i]] = Sh::enc(f[i] * c.sf);
+        for (int i = 0; i < 9; ++i) P.fm[i * pitch + dst[i]] = Sh::enc(f[i] * c.sf);
+    }
+    // next to walls: the crossing directions go to the opposite planes at o
+    // (dst[0] == o); the stored values still sum to mfix at this node's share
+    static __device__ __forceinline__ void store_bb(const Pop& P, int64_t pitch, const uint32_t* dst,
+                                                    uint32_t o, int bb, const Coef<float>& c, const float* g,
+                                                    const float* f, int64_t mfix) {
+        double s = 0.0;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            const bool cr = crosses(i + 1, bb);
+            const int64_t pl = cr ? opposite(i + 1) : i + 1;
+            const uint16_t code = Sh::enc(g[i + 1] * c.sg);
+            P.gm[(pl - 1) * pitch + (cr ? o : dst[i + 1])] = code;
+            s += gfix(c, code);
+        }
+        P.g0[dst[0]] = mfix - (int64_t)s;
+#pragma unroll
+        for (int i = 0; i < 9; ++i) {
+            const bool cr = crosses(i, bb);
+            const int64_t pl = cr ? opposite(i) : i;
+            P.fm[pl * pitch + (cr ? o : dst[i])] = Sh::enc(f[i] * c.sf);
+        }
     }
 };
 template <> struct Access<StF16> : AccessHalf<StF16> {};
@@ -444,7 +480,7 @@ __global__ __launch_bounds__(TileCfg<TY>::NT) void k_tile(const Job<S>* __restri
     __shared__ R sSx[H1 * W1];
     __shared__ R sSy[H1 * W1];
     __shared__ R sw[H1 * W1];
-    __shared__ int s_col[W3];                     // periodic x of LDS column lx (x0 + lx - 3)
+    __shared__ int s_col[W3];                     // x of LDS column lx (x0 + lx - 3), periodic or mirrored
     __shared__ int s_row[H3];                     // y * nx of LDS row ly (y0 + ly - 3), periodic or mirrored
     __shared__ double sred[NW][NPART];
     __shared__ long long sired[NW];
@@ -465,15 +501,19 @@ __global__ __launch_bounds__(TileCfg<TY>::NT) void k_tile(const Job<S>* __restri
     const R* __restrict__ st = J.stat;
     const int x0 = te.x0, y0 = te.y0;
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-    const int walls = WALL ? J.walls : 0;
+    // walls this tile can see: only tiles whose 3-node halo reaches past the
+    // domain edge read ghost nodes or hold wall nodes
+    int walls = WALL ? J.walls : 0;
+    if (WALL && y0 >= 3 && y0 + TY + 3 <= ny) walls &= ~1;
+    if (WALL && x0 >= 3 && x0 + TX + 3 <= nx) walls &= ~2;
 
     // index tables (the only integer divisions of the kernel); with walls a
-    // row outside the domain reads its mirror image (ghost rows)
+    // row or column outside the domain reads its mirror image (ghost nodes)
     for (int i = tid; i < W3 + H3; i += NTH) {
         if (i < W3)
-            s_col[i] = wrapi(x0 + i - 3, nx);
+            s_col[i] = imgof(x0 + i - 3, nx, walls & 2);
         else
-            s_row[i - W3] = rowof(y0 + (i - W3) - 3, ny, walls) * nx;
+            s_row[i - W3] = imgof(y0 + (i - W3) - 3, ny, walls & 1) * nx;
     }
     __syncthreads();
 
@@ -544,9 +584,11 @@ __global__ __launch_bounds__(TileCfg<TY>::NT) void k_tile(const Job<S>* __restri
         if (MODE != MODE_INIT && p < H1 * W1) {
             const int ly = p / W1, lx = p - ly * W1;
             const uint32_t o = (uint32_t)(s_row[ly + 2] + s_col[lx + 2]);
-            // ghost rows hold the mirrored no-slip velocity: both components odd
-            const int yy = y0 + ly - 1;
-            const R sg = (walls && (yy < 0 || yy >= ny)) ? R(-1) : R(1);
+            // ghost nodes hold the mirrored no-slip velocity: both components
+            // odd under each mirror (even at a corner)
+            const int yy = y0 + ly - 1, xx = x0 + lx - 1;
+            const bool gy = (walls & 1) && (yy < 0 || yy >= ny), gx = (walls & 2) && (xx < 0 || xx >= nx);
+            const R sg = gx != gy ? R(-1) : R(1);
             cux[k] = sg * hprev[pitch + o];
             cuy[k] = sg * hprev[2 * pitch + o];
         }
@@ -638,13 +680,16 @@ __global__ __launch_bounds__(TileCfg<TY>::NT) void k_tile(const Job<S>* __restri
         // density and viscosity laws (Eq. rho) on phi clamped to [-1, 1]
         const R rho = c.srho + c.drho * clamp1(ph);
         const R muv = c.smu + c.dmu * clamp1(ph);
-        // neighbours for the push (periodic; the rows next to a wall reflect
-        // what would cross it, below)
-        const int xe = x + 1 == nx ? 0 : x + 1, xw = x == 0 ? nx - 1 : x - 1;
-        const bool wall_s = walls && y == 0, wall_n = walls && y == ny - 1;
+        // neighbours for the push (periodic); bb: the walls next to this node
+        // (bit 0 below, 1 above, 2 left, 3 right), whose crossing populations
+        // are reflected at the store, and across which neighbours mirror
+        const int bb = !WALL ? 0
+                             : ((walls & 1) && y == 0 ? 1 : 0) | ((walls & 1) && y == ny - 1 ? 2 : 0) |
+                                   ((walls & 2) && x == 0 ? 4 : 0) | ((walls & 2) && x == nx - 1 ? 8 : 0);
+        const int xe = x + 1 == nx ? ((bb & 8) ? x : 0) : x + 1, xw = x == 0 ? ((bb & 4) ? 0 : nx - 1) : x - 1;
         const uint32_t rc = (uint32_t)y * (uint32_t)nx;
-        const uint32_t rn = (uint32_t)(y + 1 == ny ? (wall_n ? y : 0) : y + 1) * (uint32_t)nx;
-        const uint32_t rs = (uint32_t)(y == 0 ? (wall_s ? 0 : ny - 1) : y - 1) * (uint32_t)nx;
+        const uint32_t rn = (uint32_t)(y + 1 == ny ? ((bb & 2) ? y : 0) : y + 1) * (uint32_t)nx;
+        const uint32_t rs = (uint32_t)(y == 0 ? ((bb & 1) ? 0 : ny - 1) : y - 1) * (uint32_t)nx;
 
         if (MODE == MODE_INIT) {
             // Procedure step 1: g = g^eq, f = f^eq at P = 0 with the given u.
@@ -693,7 +738,8 @@ __global__ __launch_bounds__(TileCfg<TY>::NT) void k_tile(const Job<S>* __restri
             own = J.owner[o];
             if (own >= 0) {
                 const double* q = J.parts + own * PSTRIDE;
-                const double rx = perd((double)x - q[PX], nx), ry = perdy((double)y - q[PY], ny, walls);
+                const double rx = perdw((double)x - q[PX], nx, walls & 2);
+                const double ry = perdw((double)y - q[PY], ny, walls & 1);
                 usolx = (R)(q[PUX] - q[POM] * ry);
                 usoly = (R)(q[PUY] + q[POM] * rx);
                 const R cth = (R)q[PCOS];
@@ -843,25 +889,23 @@ __global__ __launch_bounds__(TileCfg<TY>::NT) void k_tile(const Job<S>* __restri
         hermite_inv(c, m, fk);
 
         // ---- push to the other copy, periodic ----
-        // Next to a wall (halfway bounce-back) the three populations that
-        // would cross it return to this node in the opposite directions.
+        // Next to a wall (halfway bounce-back) the populations that would
+        // cross it return to this node in the opposite directions.
         uint32_t dst[9];
         dst[0] = o;
         dst[1] = rc + xe;
-        dst[2] = wall_n ? o : rn + x;
+        dst[2] = rn + x;
         dst[3] = rc + xw;
-        dst[4] = wall_s ? o : rs + x;
-        dst[5] = wall_n ? o : rn + xe;
-        dst[6] = wall_n ? o : rn + xw;
-        dst[7] = wall_s ? o : rs + xw;
-        dst[8] = wall_s ? o : rs + xe;
+        dst[4] = rs + x;
+        dst[5] = rn + xe;
+        dst[6] = rn + xw;
+        dst[7] = rs + xw;
+        dst[8] = rs + xe;
         // relative rest population: g_0 - phi^n with phi^n the value written
         // to history below; (php - ph) is exact for nearby values
         if (S::kRel) gk[0] += php - ph;
-        if (wall_s)
-            A::template store<WALL_S>(J.pop[par ^ 1], pitch, dst, c, gk, fk, mk);
-        else if (wall_n)
-            A::template store<WALL_N>(J.pop[par ^ 1], pitch, dst, c, gk, fk, mk);
+        if (WALL && bb)
+            A::store_bb(J.pop[par ^ 1], pitch, dst, o, bb, c, gk, fk, mk);
         else
             A::store(J.pop[par ^ 1], pitch, dst, c, gk, fk, mk);
         R* hw = J.hist[par ^ 1];
@@ -933,9 +977,9 @@ __global__ __launch_bounds__(NT) void k_lap_psi(R* __restrict__ st, int64_t pitc
     if (o >= (int64_t)nx * ny) return;
     const int y = (int)(o / nx), x = (int)(o - (int64_t)y * nx);
     const R* psi = st + pitch;
-    const int xe = x + 1 == nx ? 0 : x + 1, xw = x == 0 ? nx - 1 : x - 1;
-    const int64_t rc = (int64_t)y * nx, rn = (int64_t)rowof(y + 1, ny, walls) * nx;
-    const int64_t rs = (int64_t)rowof(y - 1, ny, walls) * nx;
+    const int xe = imgof(x + 1, nx, walls & 2), xw = imgof(x - 1, nx, walls & 2);
+    const int64_t rc = (int64_t)y * nx, rn = (int64_t)imgof(y + 1, ny, walls & 1) * nx;
+    const int64_t rs = (int64_t)imgof(y - 1, ny, walls & 1) * nx;
     const R c4 = R(4) * psi[o];
     const R ax = (psi[rc + xe] + psi[rc + xw]) + (psi[rn + x] + psi[rs + x]);
     const R dg = (psi[rn + xe] + psi[rn + xw]) + (psi[rs + xe] + psi[rs + xw]);
@@ -979,7 +1023,7 @@ __global__ __launch_bounds__(PT_NT) void k_part_static(const double* __restrict_
         if (k < np) {
             const double* q = parts + k * PSTRIDE;
             const double reach = q[PRAD] + PCUT * D + 1.0;  // + the halo of the Laplacian
-            const double dx = fabs(perd(cx - q[PX], nx)), dy = fabs(perdy(cy - q[PY], ny, walls));
+            const double dx = fabs(perdw(cx - q[PX], nx, walls & 2)), dy = fabs(perdw(cy - q[PY], ny, walls & 1));
             h = dx <= 0.5 * PT_X + reach && dy <= 0.5 * PT_Y + reach;
         }
         const unsigned long long m = __ballot(h);
@@ -1001,7 +1045,7 @@ __global__ __launch_bounds__(PT_NT) void k_part_static(const double* __restrict_
     if (cnt == 0 && !was) return;  // uniform: nothing here changed
     for (int i = tid; i < HH * HW; i += PT_NT) {
         const int ly = i / HW, lx = i - ly * HW;
-        const int x = wrapi(x0 + lx - 1, nx), y = rowof(y0 + ly - 1, ny, walls);
+        const int x = imgof(x0 + lx - 1, nx, walls & 2), y = imgof(y0 + ly - 1, ny, walls & 1);
         const int64_t o = (int64_t)y * nx + x;
         // the indicator in the storage's arithmetic (FP64 for FP64 storage)
         R sum = base[o], best = sum, cth = base[pitch + o];
@@ -1009,7 +1053,7 @@ __global__ __launch_bounds__(PT_NT) void k_part_static(const double* __restrict_
         for (int j = 0; j < cnt; ++j) {
             const int k = list[j];
             const double* q = parts + k * PSTRIDE;
-            const R dx = (R)perd(x - q[PX], nx), dy = (R)perdy(y - q[PY], ny, walls);
+            const R dx = (R)perdw(x - q[PX], nx, walls & 2), dy = (R)perdw(y - q[PY], ny, walls & 1);
             const R rad = (R)q[PRAD], cut = rad + (R)(PCUT * D);
             // clearly outside the support: skip the square root and tanh
             if (dx * dx + dy * dy > cut * cut * R(1.000001)) continue;
@@ -1060,17 +1104,21 @@ __global__ __launch_bounds__(PR_NT) void k_part_reduce(const double* __restrict_
     const int k = blockIdx.x / PR_CH, band = blockIdx.x % PR_CH, tid = threadIdx.x;
     const double* q = parts + k * PSTRIDE;
     const double reach = q[PRAD] + PCUT * D;
-    const int xl = (int)ceil(q[PX] - reach);
-    int yl = (int)ceil(q[PY] - reach);
+    int xl = (int)ceil(q[PX] - reach), yl = (int)ceil(q[PY] - reach);
     int w = (int)floor(q[PX] + reach) - xl + 1, h = (int)floor(q[PY] + reach) - yl + 1;
-    if (walls) {  // no image in y: the box is cut at the walls
+    if (walls & 2) {  // no image in x: the box is cut at the walls
+        const int xh = xl + w - 1 < nx - 1 ? xl + w - 1 : nx - 1;
+        xl = xl > 0 ? xl : 0;
+        w = xh >= xl ? xh - xl + 1 : 0;
+    }
+    if (walls & 1) {  // likewise in y
         const int yh = yl + h - 1 < ny - 1 ? yl + h - 1 : ny - 1;
         yl = yl > 0 ? yl : 0;
         h = yh >= yl ? yh - yl + 1 : 0;
     }
     // a box narrower than the domain holds each node once, and there the plain
     // difference is the nearest periodic image
-    const bool wrap_x = w >= nx, wrap_y = !walls && h >= ny;
+    const bool wrap_x = !(walls & 2) && w >= nx, wrap_y = !(walls & 1) && h >= ny;
     w = wrap_x ? nx : w;
     h = wrap_y ? ny : h;
     const int r0 = band * h / PR_CH, r1 = (band + 1) * h / PR_CH;
@@ -1118,7 +1166,7 @@ struct PartParams {
     double wall[4];                      // wall planes y0, y1, x0, x1
     int walls;                           // bit w: wall[w] present
     int nx, ny;
-    int bounce_y;                        // bounce-back walls: no periodic image in y
+    int bounce_x, bounce_y;              // bounce-back walls: no periodic image in x, y
 };
 
 // Procedure steps 8 and 10: Eq. (particle) by explicit Euler (dt = 1, every
@@ -1155,8 +1203,10 @@ __global__ __launch_bounds__(PU_NT) void k_part_update(const double* parts, cons
                 // far pairs (no image within the threshold) contribute nothing
                 const double lim = R + qj[PRAD] + pp.xi;
                 const double ax = fabs(q[PX] - qj[PX]), ay = fabs(q[PY] - qj[PY]);
-                if ((ax > lim && pp.nx - ax > lim) || (ay > lim && (pp.bounce_y || pp.ny - ay > lim))) continue;
-                const double dx = perd(q[PX] - qj[PX], pp.nx), dy = perdy(q[PY] - qj[PY], pp.ny, pp.bounce_y);
+                if ((ax > lim && (pp.bounce_x || pp.nx - ax > lim)) || (ay > lim && (pp.bounce_y || pp.ny - ay > lim)))
+                    continue;
+                const double dx = perdw(q[PX] - qj[PX], pp.nx, pp.bounce_x);
+                const double dy = perdw(q[PY] - qj[PY], pp.ny, pp.bounce_y);
                 const double m = rep_scale(hypot(dx, dy), R + qj[PRAD], pp.xi, pp.eps);
                 sx += m * dx;
                 sy += m * dy;
@@ -1204,7 +1254,7 @@ __global__ __launch_bounds__(PU_NT) void k_part_update(const double* parts, cons
         }
         n[PX] = q[PX] + q[PUX];
         n[PY] = q[PY] + q[PUY];
-        n[PX] -= pp.nx * floor(n[PX] / pp.nx);
+        if (!pp.bounce_x) n[PX] -= pp.nx * floor(n[PX] / pp.nx);
         if (!pp.bounce_y) n[PY] -= pp.ny * floor(n[PY] / pp.ny);
         o7[QFX] = a[0];
         o7[QFY] = a[1];

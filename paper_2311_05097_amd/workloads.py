@@ -31,8 +31,9 @@ PAPER_DEFAULTS = dict(
     # free particles: repulsion threshold and stiffness (eps <= 0: none),
     # wall planes for the particle-wall repulsion (bit 0: y0, 1: y1, 2: x0, 3: x1)
     rep_xi=0.0, rep_eps=0.0, walls=0, wall_x0=0.0, wall_x1=0.0, wall_y0=0.0, wall_y1=0.0,
-    # no-flux (bounce-back) walls below the first and above the last row
-    bounce_y=0,
+    # no-flux (bounce-back) walls below the first and above the last row,
+    # left of the first and right of the last column
+    bounce_y=0, bounce_x=0,
 )
 
 # Columns of a particle array: centre, translational and angular velocity,

@@ -167,3 +167,94 @@ def test_walled_and_periodic_domains_in_one_batch(gpu):
         for u, v in zip(q.read(), solo.read()):
             assert np.array_equal(u, v)
     assert not np.array_equal(a.read()[0], b.read()[0])
+
+
+def box_case(bx=1, by=1, nx=67, ny=45):
+    """Walls in x (and y): a drop in the lower left corner, one at the right
+    wall, one at the upper wall, a wetting cylinder, gravity with a sideways
+    component and a swirling initial flow; ragged in both directions."""
+    y, x = np.mgrid[0:ny, 0:nx].astype(float)
+    phi = np.maximum(np.tanh((10.0 - np.hypot(x + 0.5, y + 0.5)) / 1.5),
+                     np.tanh((6.0 - np.hypot(x - (nx - 8.0), y - 20.0)) / 1.5))
+    phi = np.maximum(phi, np.tanh((5.0 - np.hypot(x - 30.0, y - (ny - 2.0))) / 1.5))
+    ux = 0.003 * np.sin(np.pi * (y + 0.5) / ny)
+    uy = -0.002 * np.sin(np.pi * (x + 0.5) / nx)
+    p = W.params(nx, ny, bounce_x=bx, bounce_y=by, rho1=1.0, rho2=0.3, mu1=0.1, mu2=0.04, gy=-1e-5, gx=3e-6,
+                 rho_ref=0.5, D=3.0)
+    z = W.indicator(4.0 - np.hypot(x - 45.0, y - 14.0), 3.0)
+    return p, phi, z, np.full((ny, nx), 0.3), ux, uy
+
+
+def _box_pair(gpu, storage, steps, tile, bx=1, by=1):
+    from oracle.oracle import Oracle
+    p, phi, z, ct, ux, uy = box_case(bx, by)
+    o = Oracle(p, phi, z, ct, ux, uy)
+    d = gpu.Domain(p, phi, z, ct, ux, uy, storage=storage, tile=tile)
+    o.step(steps)
+    d.step(steps)
+    errs = {n: rel(a, b) for n, a, b in zip(("phi", "ux", "uy", "P"), d.read(), o.read())}
+    print(f"\nbox x={bx} y={by} {storage} tile {tile} {steps} steps: "
+          + " ".join(f"{k}={v:.2e}" for k, v in errs.items()))
+    return d, o, errs
+
+
+@pytest.mark.parametrize("bx,by,tile", [(1, 1, 8), (1, 0, 16), (1, 1, 4)])
+def test_side_walls_and_closed_box_fp64_parity(gpu, bx, by, tile):
+    d, o, errs = _box_pair(gpu, "fp64", 300, tile, bx, by)
+    for k, e in errs.items():
+        assert e <= 1e-12, (k, e)
+
+
+def test_closed_box_fp32_parity_and_tiles_bitwise(gpu):
+    d, o, errs = _box_pair(gpu, "fp32", 300, 8)
+    for k, e in errs.items():
+        assert e <= 1e-5, (k, e)
+    p, phi, z, ct, ux, uy = box_case()
+    ref = None
+    for ty in (4, 8, 16, 32):
+        d = gpu.Domain(p, phi, z, ct, ux, uy, storage="fp32", tile=ty)
+        d.step(41)
+        got = d.read()
+        if ref is None:
+            ref = got
+        else:
+            for a, b in zip(got, ref):
+                assert np.array_equal(a, b), ty
+
+
+def test_closed_box_fp16dev_exact_mass(gpu):
+    d, o, errs = _box_pair(gpu, "fp16dev", 300, 16)
+    assert errs["phi"] <= 1e-3
+    p, phi, z, ct, ux, uy = box_case()
+    d0 = gpu.Domain(p, phi, z, ct, ux, uy, storage="fp16dev", tile=16)
+    assert d.mass() == d0.mass()
+
+
+def test_particles_in_a_closed_box_fp64(gpu):
+    """Particles next to every wall of a closed box (repulsion planes on the
+    wall lines), one of prescribed motion; fields, state and forces against
+    the oracle."""
+    from oracle.oracle import Oracle
+    nx, ny = 67, 45
+    p = W.params(nx, ny, bounce_x=1, bounce_y=1, rho2=0.5, mu2=0.05, gy=-2e-5, gx=4e-6, rho_ref=0.5,
+                 rep_xi=2.0, rep_eps=50.0, walls=15, wall_y0=-0.5, wall_y1=ny - 0.5, wall_x0=-0.5,
+                 wall_x1=nx - 0.5)
+    D = p["D"]
+    parts = np.array([W.particle(5.1, 5.2, 5.5, 1.6, 60.0, ux=-0.002, uy=-0.003),
+                      W.particle(61.5, 38.9, 6.0, 0.9, 120.0, omega=1e-3, ux=0.003),
+                      W.particle(30.0, 22.0, 4.0, -1.0, 75.0, ux=0.001, omega=-2e-3)])
+    y, x = np.mgrid[0:ny, 0:nx].astype(float)
+    phi = np.tanh((22.0 - y) / (D / 2))
+    for q in parts:
+        phi *= 1.0 - W.indicator(q[5] - np.hypot(x - q[0], y - q[1]), D)
+    z = np.zeros_like(phi)
+    o = Oracle(p, phi, z, None, None, None, particles=parts)
+    d = gpu.Domain(p, phi, z, storage="fp64", tile=16, particles=parts)
+    o.step(300)
+    d.step(300)
+    for a, b in zip(d.read(), o.read()):
+        assert rel(a, b) <= 1e-12
+    ds, do = d.particles()
+    os_, oo = o.particles()
+    assert np.abs(ds - os_).max() <= 1e-10
+    assert np.abs(do[:, :3] - oo[:, :3]).max() <= 1e-10 * np.abs(oo[:, :3]).max()
