@@ -156,6 +156,27 @@ int lbm_create_particles(const lbm_params *p, void *dev_workspace, size_t bytes,
  * Errors: LBM_EINVAL (NULL domain), LBM_ESTATE (failed finiteness check). */
 int lbm_particles(lbm_domain *d, double *state, double *outputs);
 
+/* Voxel solids.  Sec. 4.1 smooths its binary micro-CT solid by a few
+ * iterations of a standard Cahn-Hilliard equation before using it as the
+ * indicator phi0.  This runs `iters` explicit steps of
+ *     d chi/dt = lap mu,  mu = chi^3 - chi - (D^2/8) lap chi
+ * on chi = 2 solid - 1 (the planar equilibrium tanh(2 z / D) is the
+ * indicator profile of Sec. 2.1), with the isotropic Laplacian, periodic or
+ * mirrored at the walls of p->bounce_x / p->bounce_y, and writes
+ * phi0 = clamp((1 + chi)/2, 0, 1), ready for lbm_create.  dtau <= 0 takes
+ * half the stability limit of the step linearised about chi = +-1,
+ * 1 / (2 (kappa L^2 + 2 L)), L = 16/3.  Uses p->nx, ny, D, bounce_x,
+ * bounce_y (the rest of p must be valid).  solid, phi0: host [ny][nx]
+ * doubles (solid in [0, 1], 1 = solid); the device workspace holds three
+ * FP64 planes (lbm_smooth_workspace_bytes; 0 for invalid sizes), 256-byte
+ * aligned, free for reuse once the call returns.  Blocks.
+ * Errors: LBM_EINVAL (params, NULL pointers, iters outside 0..2^20,
+ * non-finite dtau, unaligned workspace), LBM_ENOMEM (workspace too small),
+ * LBM_EDEVICE. */
+size_t lbm_smooth_workspace_bytes(int32_t nx, int32_t ny);
+int lbm_smooth_solid(const lbm_params *p, int32_t iters, double dtau, void *dev_workspace, size_t bytes,
+                     void *hip_stream, const double *solid, double *phi0);
+
 /* Procedure steps 2-6, nsteps >= 0 times: one fused kernel per step (stencils
  * for mu, grad phi, S and F_c from a halo tile, velocity and pressure
  * recovery, both MRT collisions, streaming).  Enqueued on the stream; returns

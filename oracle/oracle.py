@@ -93,6 +93,12 @@ def lib():
         L.orc_get_field.restype = ctypes.c_int
         L.orc_get_pops.argtypes = [ctypes.c_void_p, _D, _D]
         L.orc_mass.argtypes = [ctypes.c_void_p]
+        L.orc_vox_dtau.argtypes = [ctypes.c_double]
+        L.orc_vox_dtau.restype = ctypes.c_double
+        L.orc_smooth_solid.argtypes = [ctypes.c_int] * 4 + [ctypes.c_double, ctypes.c_int, ctypes.c_double,
+                                                             _D, _D]
+        L.orc_smooth_chi.argtypes = [ctypes.c_int] * 4 + [ctypes.c_double, ctypes.c_int, ctypes.c_double,
+                                                           _D, _D]
         L.orc_mass.restype = ctypes.c_double
         L.orc_energy.argtypes = [ctypes.c_void_p, _D, _D]
         L.orc_lattice.argtypes = [ctypes.c_double, _D, ctypes.POINTER(ctypes.c_int),
@@ -200,6 +206,28 @@ def mu(params: dict, phi, phi0, psi):
     out = np.zeros_like(phi)
     op = make_params(p)
     lib().orc_mu(ctypes.byref(op), _ptr(phi), _ptr(phi0), _ptr(psi), _ptr(out))
+    return out
+
+
+def vox_dtau(D: float) -> float:
+    return lib().orc_vox_dtau(D)
+
+
+def smooth_solid(solid, D: float, iters: int = 20, dtau: float = 0.0, bounce_x: int = 0,
+                 bounce_y: int = 0) -> np.ndarray:
+    """phi0 from a voxel solid (R-VOX)."""
+    s = _c64(solid)
+    ny, nx = s.shape
+    out = np.zeros_like(s)
+    lib().orc_smooth_solid(nx, ny, int(bounce_x), int(bounce_y), D, int(iters), dtau, _ptr(s), _ptr(out))
+    return out
+
+
+def smooth_chi(chi, D: float, iters: int, dtau: float = 0.0, bounce_x: int = 0, bounce_y: int = 0):
+    c = _c64(chi)
+    ny, nx = c.shape
+    out = np.zeros_like(c)
+    lib().orc_smooth_chi(nx, ny, int(bounce_x), int(bounce_y), D, int(iters), dtau, _ptr(c), _ptr(out))
     return out
 
 

@@ -611,6 +611,46 @@ int lbm_create_particles(const lbm_params* p, void* dev_workspace, size_t bytes,
     return create_common(p, dev_workspace, bytes, hip_stream, phi, phi0, cos_theta, ux, uy, particles, out);
 }
 
+size_t lbm_smooth_workspace_bytes(int32_t nx, int32_t ny) {
+    if (nx < 8 || ny < 8 || (int64_t)nx * ny >= (int64_t)1 << 31) return 0;
+    return 3 * up((size_t)nx * ny * 8);
+}
+
+int lbm_smooth_solid(const lbm_params* p, int32_t iters, double dtau, void* dev_workspace, size_t bytes,
+                     void* hip_stream, const double* solid, double* phi0) {
+    int rc = validate(p);
+    if (rc) return rc;
+    if (!solid || !phi0 || !dev_workspace) return fail(LBM_EINVAL, "NULL argument");
+    if (iters < 0 || iters > (1 << 20)) return fail(LBM_EINVAL, "iters out of range");
+    if (!std::isfinite(dtau)) return fail(LBM_EINVAL, "dtau must be finite");
+    if ((uintptr_t)dev_workspace % ALIGN) return fail(LBM_EINVAL, "workspace must be 256-byte aligned");
+    const size_t need = lbm_smooth_workspace_bytes(p->nx, p->ny);
+    if (bytes < need) return fail(LBM_ENOMEM, "workspace too small");
+    const int64_t N = (int64_t)p->nx * p->ny;
+    const double kappa = p->D * p->D / 8.0, L = 16.0 / 3.0;
+    // default: half the stability limit of the step linearised about chi = +-1
+    if (dtau <= 0.0) dtau = 0.5 / (kappa * L * L + 2.0 * L);
+    hipStream_t st = (hipStream_t)hip_stream;
+    char* ws = (char*)dev_workspace;
+    double* chi = (double*)ws;
+    double* mu = (double*)(ws + up((size_t)N * 8));
+    double* nxt = (double*)(ws + 2 * up((size_t)N * 8));
+    const unsigned nb = (unsigned)((N + NT - 1) / NT);
+    const int w = wall_bits(*p);
+    HIPCHK(hipMemcpyAsync(nxt, solid, (size_t)N * 8, hipMemcpyHostToDevice, st));
+    hipLaunchKernelGGL(k_vox, dim3(nb), dim3(NT), 0, st, nxt, nullptr, chi, p->nx, p->ny, w, kappa, dtau, 0);
+    for (int32_t it = 0; it < iters; ++it) {
+        hipLaunchKernelGGL(k_vox, dim3(nb), dim3(NT), 0, st, chi, nullptr, mu, p->nx, p->ny, w, kappa, dtau, 1);
+        hipLaunchKernelGGL(k_vox, dim3(nb), dim3(NT), 0, st, chi, mu, nxt, p->nx, p->ny, w, kappa, dtau, 2);
+        std::swap(chi, nxt);
+    }
+    hipLaunchKernelGGL(k_vox, dim3(nb), dim3(NT), 0, st, chi, nullptr, nxt, p->nx, p->ny, w, kappa, dtau, 3);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipMemcpyAsync(phi0, nxt, (size_t)N * 8, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    return LBM_OK;
+}
+
 int lbm_particles(lbm_domain* d, double* state, double* outputs) {
     int rc = usable(d);
     if (rc) return rc;

@@ -1271,6 +1271,43 @@ __global__ __launch_bounds__(PU_NT) void k_part_update(const double* parts, cons
     }
 }
 
+// ------------------------------------------------------------ voxel solids
+// A binary (voxel) solid is smoothed before it serves as phi0 by a few
+// explicit steps of the standard Cahn-Hilliard equation on chi = 2 s - 1
+// (Sec. 4.1 smooths its micro-CT solid this way): d chi/dt = lap mu,
+// mu = chi^3 - chi - kappa lap chi, kappa = D^2/8 (planar equilibrium
+// tanh(2 z / D), the indicator profile), isotropic Laplacian, periodic or
+// mirrored at walls (bit 0: walls in y, 1: in x).  FP64: a one-off pass.
+__device__ __forceinline__ double vox_lap(const double* c, int x, int y, int nx, int ny, int walls) {
+    const int xe = imgof(x + 1, nx, walls & 2), xw = imgof(x - 1, nx, walls & 2);
+    const int64_t rc = (int64_t)y * nx, rn = (int64_t)imgof(y + 1, ny, walls & 1) * nx;
+    const int64_t rs = (int64_t)imgof(y - 1, ny, walls & 1) * nx;
+    const double c4 = 4.0 * c[rc + x];
+    const double ax = (c[rc + xe] + c[rc + xw]) + (c[rn + x] + c[rs + x]);
+    const double dg = (c[rn + xe] + c[rn + xw]) + (c[rs + xe] + c[rs + xw]);
+    return (ax - c4) * (2.0 / 3.0) + (dg - c4) * (1.0 / 6.0);
+}
+// mode 0: chi = 2 s - 1; 1: mu from chi; 2: chi += dtau lap mu (into out);
+// 3: phi0 = clamp((1 + chi)/2, 0, 1)
+__global__ __launch_bounds__(NT) void k_vox(const double* __restrict__ a, const double* __restrict__ b,
+                                            double* __restrict__ out, int nx, int ny, int walls, double kappa,
+                                            double dtau, int mode) {
+    const int64_t o = (int64_t)blockIdx.x * NT + threadIdx.x;
+    if (o >= (int64_t)nx * ny) return;
+    const int y = (int)(o / nx), x = (int)(o - (int64_t)y * nx);
+    if (mode == 0) {
+        out[o] = 2.0 * a[o] - 1.0;
+    } else if (mode == 1) {
+        const double c = a[o];
+        out[o] = c * c * c - c - kappa * vox_lap(a, x, y, nx, ny, walls);
+    } else if (mode == 2) {
+        out[o] = a[o] + dtau * vox_lap(b, x, y, nx, ny, walls);
+    } else {
+        const double z = (1.0 + a[o]) * 0.5;
+        out[o] = z < 0.0 ? 0.0 : (z > 1.0 ? 1.0 : z);
+    }
+}
+
 // Fixed-order sum of the per-tile partials: res[k] = sum_i part[i][k],
 // res[NPART] = exact fixed-point mass (16-bit modes) as a double-rounded value
 // and ires[0] its 64-bit integer.

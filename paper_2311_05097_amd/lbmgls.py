@@ -26,7 +26,7 @@ EXPORTED = [
     "lbm_export_state", "lbm_import_state", "lbm_last_step_ms", "lbm_destroy",
     "lbm_batch_workspace_bytes", "lbm_batch_create", "lbm_batch_add", "lbm_batch_remove",
     "lbm_batch_step", "lbm_batch_size", "lbm_batch_destroy", "lbm_last_error",
-    "lbm_create_particles", "lbm_particles",
+    "lbm_create_particles", "lbm_particles", "lbm_smooth_workspace_bytes", "lbm_smooth_solid",
 ]
 
 
@@ -103,6 +103,9 @@ def lib():
             "lbm_create_particles": (ctypes.c_int, [P, _VP, ctypes.c_size_t, _VP, _D, _D, _D, _D, _D, _D,
                                                     ctypes.POINTER(_VP)]),
             "lbm_particles": (ctypes.c_int, [_VP, _D, _D]),
+            "lbm_smooth_workspace_bytes": (ctypes.c_size_t, [ctypes.c_int32, ctypes.c_int32]),
+            "lbm_smooth_solid": (ctypes.c_int, [P, ctypes.c_int32, ctypes.c_double, _VP, ctypes.c_size_t, _VP,
+                                                _D, _D]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(L, name)
@@ -279,6 +282,23 @@ class Domain:
     def import_state(self, state: bytes):
         buf = ctypes.create_string_buffer(state, len(state))
         _check(lib().lbm_import_state(self._h, ctypes.cast(buf, _VP), len(state)))
+
+
+def smooth_solid(params: dict, solid, iters: int = 20, dtau: float = 0.0):
+    """phi0 from a voxel solid by `iters` steps of the smoothing
+    Cahn-Hilliard equation on the GPU (lbm_smooth_solid); params supplies
+    nx, ny, D and the walls."""
+    solid, sp = _arr(solid, (params["ny"], params["nx"]))
+    nbytes = lib().lbm_smooth_workspace_bytes(int(params["nx"]), int(params["ny"]))
+    if nbytes == 0:
+        raise LbmError(-1, "invalid grid size")
+    buf, ptr = alloc_workspace(nbytes)
+    out = np.zeros_like(solid)
+    lp = make_params(params)
+    _check(lib().lbm_smooth_solid(ctypes.byref(lp), int(iters), float(dtau), _VP(ptr), nbytes,
+                                  current_stream_handle(), sp, out.ctypes.data_as(_D)))
+    del buf
+    return out
 
 
 class Batch:

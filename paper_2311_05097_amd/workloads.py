@@ -261,6 +261,30 @@ def porous_random(n: int = 256, n_obstacles: int = 20, seed: int = 1, theta_deg:
                     _zeros(n, n), _zeros(n, n), dict(seed=seed))
 
 
+def voxel_solid(nx: int = 256, ny: int = 256, n_grains: int = 40, seed: int = 7,
+                r_range=(6.0, 18.0), periodic: bool = True) -> np.ndarray:
+    """Synthetic stand-in for a segmented micro-CT image (Sec. 4.1): a binary
+    voxel solid (1 in the grains, 0 in the pores) of random disks, rasterised
+    node by node, with the staircase boundaries of voxel data.  Draw order per
+    grain: r, x, y.  With periodic=False the disks are not wrapped."""
+    rng = np.random.default_rng(seed)
+    s = np.zeros((ny, nx))
+    for _ in range(n_grains):
+        r = rng.uniform(*r_range)
+        cx, cy = rng.uniform(0, nx), rng.uniform(0, ny)
+        # the grain's bounding box, wrapped (or cut) at the edges
+        xs = np.arange(int(np.floor(cx - r)), int(np.ceil(cx + r)) + 1)
+        ys = np.arange(int(np.floor(cy - r)), int(np.ceil(cy + r)) + 1)
+        if not periodic:
+            xs = xs[(xs >= 0) & (xs < nx)]
+            ys = ys[(ys >= 0) & (ys < ny)]
+        dx, dy = xs - cx, ys - cy
+        inside = dy[:, None] ** 2 + dx[None, :] ** 2 <= r * r
+        yy, xx = np.nonzero(inside)
+        s[ys[yy] % ny, xs[xx] % nx] = 1.0
+    return s
+
+
 def static_drop(n: int = 64, R: float = 16.0, **kw) -> Workload:
     """Free circular drop in a periodic box, no solid."""
     p = params(n, n, **kw)
