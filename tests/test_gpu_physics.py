@@ -121,3 +121,55 @@ def test_rotating_cylinder_couette(gpu):
         assert 0.5 < dlt < 6.0
         assert abs(umid - pred) <= 0.03 * pred
     assert errs[1] < 0.6 * errs[0] and errs[1] < 0.15
+
+
+def _sediment(gpu, rho1, steps, sigma=1e-2, D=2.0):
+    """Sec. 4.5: a disk (R = 0.125, rho_p = 1.25) released at (1, 4) in a
+    closed 2 x 6 channel, fluid 1 below y = 3 and fluid 2 (rho2 = 1) above,
+    mu = 0.1, g = 980, body force (rho - rho2) g; dx = 1/192, dt = dx/64.
+    Returns the history (t, y_p, v_p) in the paper's units."""
+    dx = 1 / 192
+    dt = dx / 64
+    g = 980 * dt * dt / dx
+    nx, ny = 384, 1152
+    R = 0.125 / dx
+    nu = 0.1 * dt / dx / dx
+    p = W.params(nx, ny, bounce_x=1, bounce_y=1, rho1=rho1, rho2=1.0, mu1=nu * rho1, mu2=nu, D=D, sigma=sigma,
+                 gy=-g, rho_ref=1.0, rep_xi=2.0, rep_eps=2e-3 / g, walls=15, wall_y0=-0.5, wall_y1=ny - 0.5,
+                 wall_x0=-0.5, wall_x1=nx - 0.5)
+    y, x = np.mgrid[0:ny, 0:nx].astype(float)
+    phi = np.tanh((ny / 2 - y) / (D / 2)) if rho1 != 1.0 else np.ones((ny, nx))
+    phi = phi * (1.0 - W.indicator(R - np.hypot(x - nx / 2, y - 4 / dx), D))
+    d = gpu.Domain(p, phi, np.zeros_like(phi), storage="fp32",
+                   particles=[W.particle(nx / 2, 4 / dx, R, 1.25, 90.0)])
+    hist = []
+    for k in range(steps // 2000):
+        d.step(2000)
+        st, _ = d.particles()
+        hist.append(((k + 1) * 2000 * dt, st[0, 1] * dx, st[0, 3] * dx / dt))
+    assert all(np.isfinite(a).all() for a in d.read())
+    return np.array(hist)
+
+
+def test_sedimentation_in_a_stratified_channel(gpu):
+    """The three regimes Sec. 4.5 describes, in a channel closed by
+    bounce-back walls: in one fluid the particle reaches a terminal velocity
+    and comes to rest on the bottom (held by the wall repulsion); with a
+    lower fluid lighter than the particle (rho1 = 1.1) it passes the
+    interface and also lands; with a lower fluid heavier than the particle
+    (rho1 = 1.3) it is stopped at the interface, oscillates, and comes to
+    rest there, floating below the far-field interface (y = 3)."""
+    R = 0.125
+    h = _sediment(gpu, 1.0, 20000)
+    vt = -h[:6, 2].min()
+    print(f"\nhomogeneous: terminal velocity {vt:.3f}, at rest at y = {h[-1, 1]:.4f}")
+    assert 4.5 < vt < 6.5 and abs(h[-1, 1] - R) < 0.01 and abs(h[-1, 2]) < 0.01
+    h = _sediment(gpu, 1.1, 30000)
+    print(f"rho1 = 1.1: y = {h[-1, 1]:.4f}")
+    assert abs(h[-1, 1] - R) < 0.01 and abs(h[-1, 2]) < 0.01
+    h = _sediment(gpu, 1.3, 50000)
+    late = h[h[:, 0] > 3.5]
+    print(f"rho1 = 1.3: y = {late[:, 1].min():.4f}..{late[:, 1].max():.4f}, |v| <= {np.abs(late[:, 2]).max():.3f}")
+    assert 2.6 < late[:, 1].min() and late[:, 1].max() < 2.9 and np.abs(late[:, 2]).max() < 0.1
+    # it did reach the interface first (the fall is stopped, then oscillates)
+    assert h[:, 2].max() > 1.0
