@@ -257,6 +257,9 @@ def main():
                     help="c2: the 1024^2 cylinder + drop case (default); r4096: the same physics "
                          "on 4096^2 (working set far above the last-level cache); c5: the 1024 x 2048 "
                          "pool with 64 free particles (step time includes the particle kernels)")
+    ap.add_argument("--walls", default="none", choices=["none", "y", "box"],
+                    help="close the workload with no-flux bounce-back walls: below and above (y) or on "
+                         "all four sides (box)")
     ap.add_argument("--serve", action="store_true", help="served-jobs benchmark instead")
     ap.add_argument("--jobs", type=int, default=256)
     ap.add_argument("--ratio-range", type=float, nargs=2, default=(10.0, 1000.0))
@@ -286,6 +289,8 @@ def main():
     from paper_2311_05097_amd import workloads as W
     from paper_2311_05097_amd import autotune
     w = {"c2": W.config2, "r4096": W.roofline_grid, "c5": W.pool_with_particles}[args.workload]()
+    if args.walls != "none":
+        w.params.update(bounce_y=1, bounce_x=1 if args.walls == "box" else 0)
     R = W.roofline_grid()
     nw, nr = w.params["nx"] * w.params["ny"], R.params["nx"] * R.params["ny"]
     # copy ceilings first, in a fresh allocator state
@@ -312,10 +317,10 @@ def main():
                                 "rho ratio 100, mu ratio 50, g=1e-6" % (w.meta["Rp"], w.meta["R0"])
                                 if "Rp" in w.meta else w.name),
                    "nx": w.params["nx"], "ny": w.params["ny"], "storage": args.storage,
-                   "tile": f"64x{tile}"},
+                   "tile": f"64x{tile}", "walls": args.walls},
         "roofline": roofline(args.storage, r["nodes"], r["kernel_ms"],
-                             measured_traffic(args.workload, args.storage, tile),
-                             ceil[("w", args.storage)]),
+                             measured_traffic(args.workload, args.storage, tile) if args.walls == "none"
+                             else None, ceil[("w", args.storage)]),
         "mass_drift": r["mass_drift"],
         "finite": r["finite"],
     }

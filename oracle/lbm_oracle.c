@@ -890,7 +890,7 @@ static void collide_all(orc_state *st)
     const long N = st->N;
     double **F = st->fld;
     const double d0 = p->d0;
-#pragma omp parallel for schedule(static)
+#pragma omp parallel for schedule(static) if (st->N >= 2048) /* threads only where they pay */
     for (long o = 0; o < N; ++o) {
         double gi[9], fi[9], ge[9], fe[9], G[9], F2[9], out[9], Lam[81];
         for (int i = 0; i < 9; ++i) { gi[i] = st->g[i * N + o]; fi[i] = st->f[i * N + o]; }
