@@ -738,8 +738,11 @@ __global__ __launch_bounds__(TileCfg<TY>::NT) void k_tile(const Job<S>* __restri
             own = J.owner[o];
             if (own >= 0) {
                 const double* q = J.parts + own * PSTRIDE;
-                const double rx = perdw((double)x - q[PX], nx, walls & 2);
-                const double ry = perdw((double)y - q[PY], ny, walls & 1);
+                // the domain's walls, not the tile's: a particle's support
+                // reaches tiles whose halo stays inside the domain
+                const int dw = WALL ? J.walls : 0;
+                const double rx = perdw((double)x - q[PX], nx, dw & 2);
+                const double ry = perdw((double)y - q[PY], ny, dw & 1);
                 usolx = (R)(q[PUX] - q[POM] * ry);
                 usoly = (R)(q[PUY] + q[POM] * rx);
                 const R cth = (R)q[PCOS];

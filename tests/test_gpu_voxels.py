@@ -32,6 +32,15 @@ def test_smoothing_matches_the_oracle(gpu, nx, ny, bx, by):
     assert np.abs(o - s).max() > 0.3  # it did smooth
 
 
+def test_smoothing_with_a_given_step(gpu):
+    from oracle import oracle as O
+    s = W.voxel_solid(100, 64, n_grains=10, seed=4)
+    p = W.params(100, 64, bounce_y=1)
+    g = gpu.smooth_solid(p, s, 35, dtau=0.004)
+    o = O.smooth_solid(s, p["D"], 35, dtau=0.004, bounce_y=1)
+    assert np.abs(g - o).max() <= 1e-13
+
+
 def test_smoothing_arguments(gpu):
     p = W.params(32, 32)
     with pytest.raises(gpu.LbmError):
