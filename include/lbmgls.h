@@ -60,7 +60,7 @@ enum {
 };
 
 /* Tile shapes of the fused step kernel: 64 columns x TY rows (256 threads for
- * TY <= 8, 512 for TY >= 16; 64x32 is not built for FP64). */
+ * TY = 4, 512 otherwise; 64x32 is not built for FP64). */
 enum { LBM_TILE_AUTO = 0, LBM_TILE_64x4 = 4, LBM_TILE_64x8 = 8, LBM_TILE_64x16 = 16, LBM_TILE_64x32 = 32 };
 
 typedef struct {

@@ -4,9 +4,10 @@ The step kernel is compiled for 64 x TY tiles with TY in {4, 8, 16}.  Small TY
 gives more blocks (better load balance on 256 CUs) but recomputes a larger
 share of halo; large TY amortises the 3-node halo of the order parameter.  The
 best choice depends on the grid and on the storage mode, so it is measured:
-each candidate runs a few steps on a scratch domain of the same size and
-storage (HIP-event kernel time), and the fastest is cached in a JSON file
-keyed by (nx, ny, storage).
+each candidate runs a few milliseconds of steps on a scratch domain of the
+same size and storage (HIP-event kernel time, best of two interleaved
+rounds), and the fastest is cached in a JSON file keyed by (nx, ny,
+storage).
 
 Cache: $LBMGLS_TUNE_CACHE or ~/.cache/lbmgls/tiles.json.
 """
@@ -71,7 +72,14 @@ def best_tile(params: dict, storage: str, retune: bool = False) -> int:
     cache = _load()
     if not retune and k in cache:
         return int(cache[k]["tile"])
-    times = {ty: measure(params, storage, ty) for ty in CANDIDATES}
+    # enough steps for a few milliseconds per measurement, two interleaved
+    # rounds, the better of the two per candidate (near-ties are common)
+    steps = max(40, min(400, int(2e8 // (nx * ny))))
+    times = {}
+    for _ in range(2):
+        for ty in CANDIDATES:
+            t = measure(params, storage, ty, steps=steps)
+            times[ty] = min(t, times.get(ty, t))
     best = min(times, key=times.get)
     cache[k] = {"tile": best, "ms": {str(t): round(v, 5) for t, v in times.items()}}
     _save(cache)

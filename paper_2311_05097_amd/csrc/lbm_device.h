@@ -458,11 +458,13 @@ __device__ __forceinline__ T wave_sum(T v) {
 }
 
 // ------------------------------------------------------------ tile kernel
-// Block size per tile height: 256 threads (4 wavefronts) for 64 x 4 and
-// 64 x 8 tiles, 512 (8 wavefronts) for 64 x 16 and 64 x 32.
+// Block size per tile height: 256 threads (4 wavefronts) for 64 x 4 tiles,
+// 512 (8 wavefronts) for 64 x 8, 64 x 16 and 64 x 32, i.e. one, one, two and
+// four owned nodes per thread.  (64 x 8 with 256 threads, two nodes each,
+// was slower in every storage mode and grid measured.)
 template <int TY>
 struct TileCfg {
-    static constexpr int NT = TY >= 16 ? 512 : 256;
+    static constexpr int NT = TY == 4 ? 256 : 512;
 };
 
 // Thread (lane, wave) owns the nodes (x0 + lane, y0 + wave + NW k), k < NOWN.
