@@ -64,7 +64,7 @@ enum {
 enum { LBM_TILE_AUTO = 0, LBM_TILE_64x4 = 4, LBM_TILE_64x8 = 8, LBM_TILE_64x16 = 16, LBM_TILE_64x32 = 32 };
 
 typedef struct {
-    int32_t nx, ny;        /* lattice size, periodic; nx, ny >= 8                  */
+    int32_t nx, ny;        /* lattice size (periodic unless walled); nx, ny >= 8  */
     int32_t storage;       /* LBM_STORE_*                                          */
     int32_t tile;          /* LBM_TILE_*                                           */
     double d0;             /* c_s^2 / c^2 in (0, 1); D2Q9 weights (Sec. 4)         */
