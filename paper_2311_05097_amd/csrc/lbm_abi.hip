@@ -12,6 +12,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <algorithm>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -836,6 +837,8 @@ struct lbm_batch {
 
 namespace {
 
+constexpr int64_t BATCH_CHUNK = 50;  // launches per captured batch graph
+
 void drop_graph(lbm_batch* b) {
     if (b->exec) (void)hipGraphExecDestroy(b->exec);
     if (b->graph) (void)hipGraphDestroy(b->graph);
@@ -887,39 +890,54 @@ int batch_step_impl(lbm_batch* b, int64_t nsteps, const int64_t* budget) {
         drop_graph(b);
     }
     if (b->members.empty() || nsteps == 0) return LBM_OK;
-    b->jobs.assign(js * b->members.size(), 0);
-    int32_t base = 0;
-    std::vector<int64_t> adv(b->members.size());
-    for (size_t k = 0; k < b->members.size(); ++k) {
-        lbm_domain* d = b->members[k];
+    // The graph holds a fixed chunk of BATCH_CHUNK launches and is replayed;
+    // before each replay the job table gets the chunk's first step and the
+    // number of its launches each member takes part in (the rest of its tiles
+    // return at once).  Membership changes recapture only one chunk.
+    const int64_t nchunks = (nsteps + BATCH_CHUNK - 1) / BATCH_CHUNK;
+    const size_t nm = b->members.size();
+    b->jobs.assign(js * nm * (size_t)nchunks, 0);
+    std::vector<int64_t> adv(nm);
+    for (size_t k = 0; k < nm; ++k) {
         int64_t n = nsteps;
         if (budget) n = budget[k] < n ? budget[k] : n;
         if (n < 0) n = 0;
-        if (d->failed) n = 0;
+        if (b->members[k]->failed) n = 0;
         adv[k] = n;
-        Job<S> J;
-        make_job<S>(d, (int32_t)n, d->steps, false, base, J);
-        std::memcpy(b->jobs.data() + k * js, &J, js);
-        base += (int32_t)d->tiles.size();
     }
-    HIPCHK(hipMemcpyAsync(b->ws + b->off_jobs, b->jobs.data(), b->jobs.size(), hipMemcpyHostToDevice, b->stream));
-    if (!b->exec || b->graph_steps != nsteps || b->graph_ntiles != (int)b->tiles.size()) {
+    for (int64_t c = 0; c < nchunks; ++c) {
+        int32_t base = 0;
+        for (size_t k = 0; k < nm; ++k) {
+            lbm_domain* d = b->members[k];
+            const int64_t done = std::min(c * BATCH_CHUNK, adv[k]);
+            const int64_t n = std::min(adv[k] - done, BATCH_CHUNK);
+            Job<S> J;
+            make_job<S>(d, (int32_t)n, d->steps + done, false, base, J);
+            std::memcpy(b->jobs.data() + ((size_t)c * nm + k) * js, &J, js);
+            base += (int32_t)d->tiles.size();
+        }
+    }
+    if (!b->exec || b->graph_steps != BATCH_CHUNK || b->graph_ntiles != (int)b->tiles.size()) {
         int rc;
         switch (b->ty) {
-            case 4: rc = batch_capture<S, 4>(b, nsteps); break;
-            case 16: rc = batch_capture<S, 16>(b, nsteps); break;
+            case 4: rc = batch_capture<S, 4>(b, BATCH_CHUNK); break;
+            case 16: rc = batch_capture<S, 16>(b, BATCH_CHUNK); break;
             case 32:
                 if constexpr (sizeof(typename S::R) == 4) {
-                    rc = batch_capture<S, 32>(b, nsteps);
+                    rc = batch_capture<S, 32>(b, BATCH_CHUNK);
                     break;
                 }
                 return fail(LBM_EUNSUPPORTED, "64x32 tiles are not built for FP64");
-            default: rc = batch_capture<S, 8>(b, nsteps); break;
+            default: rc = batch_capture<S, 8>(b, BATCH_CHUNK); break;
         }
         if (rc) return rc;
     }
-    HIPCHK(hipGraphLaunch(b->exec, b->stream));
-    for (size_t k = 0; k < b->members.size(); ++k) b->members[k]->steps += adv[k];
+    for (int64_t c = 0; c < nchunks; ++c) {
+        HIPCHK(hipMemcpyAsync(b->ws + b->off_jobs, b->jobs.data() + (size_t)c * nm * js, nm * js,
+                              hipMemcpyHostToDevice, b->stream));
+        HIPCHK(hipGraphLaunch(b->exec, b->stream));
+    }
+    for (size_t k = 0; k < nm; ++k) b->members[k]->steps += adv[k];
     return LBM_OK;
 }
 
