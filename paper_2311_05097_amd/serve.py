@@ -2,12 +2,18 @@
 
 A stream of jobs (each: a domain, parameters and a step budget) arrives over
 time.  The server keeps every admitted job's fields resident in GPU memory and
-advances all of them together: each tick is one ``lbm_batch_step`` (one fused
-launch per time step over the tiles of every resident job, replayed from a HIP
-graph), after which finished jobs are read out and released and queued jobs are
-admitted as memory frees up.  Admission is by HBM footprint: the sum of the
-resident jobs' workspaces stays under a byte budget.  Jobs whose fields become
-non-finite are detected after the tick (``lbm_check``) and evicted as failed.
+advances all of them in ticks, after which finished jobs are read out and
+released and queued jobs are admitted as memory frees up.  Admission is by HBM
+footprint: the sum of the resident jobs' workspaces stays under a byte budget.
+Jobs whose fields become non-finite are detected after the tick
+(``lbm_check``) and evicted as failed.
+
+The resident jobs are packed into lanes, each an ``lbm_batch`` whose members'
+workspaces together fit the GPU's last-level cache (``lane_bytes``); a tick
+steps the lanes one after another on one stream, each with one fused launch
+per time step over the tiles of all its members (replayed from a HIP graph).
+One batch over everything would stream the whole resident set from HBM every
+step; a lane's set stays in the cache for its steps.
 
 ``run_solo`` is the baseline: the same stream processed one job at a time, each
 with its own per-step launches (no batching, no graph).
@@ -78,11 +84,11 @@ def _sync():
 
 
 class Server:
-    """Continuous batching over one lbm_batch."""
+    """Continuous batching over cache-sized lanes of lbm_batch."""
 
     def __init__(self, storage: str = "fp32", budget_bytes: int = 4 << 30, tick_steps: int = 500,
                  max_members: int = 128, tile: int = 8, keep_phi: bool = False,
-                 job_overrides: dict | None = None, on_retire=None):
+                 job_overrides: dict | None = None, on_retire=None, lane_bytes: int | None = None):
         self.storage = storage
         self.budget = int(budget_bytes)
         self.tick = int(tick_steps)
@@ -90,22 +96,47 @@ class Server:
         self.keep_phi = keep_phi
         self.overrides = dict(job_overrides or {})
         self.on_retire = on_retire
-        self.batch = lbmgls.Batch(storage=storage, tile=tile, max_members=max_members,
-                                  max_tiles=max_members * (1024 * 1024 // (64 * 4)))
-        self.resident: list = []  # (JobResult, Domain, remaining, denominator, mass0)
+        # lane capacity in workspace bytes; the part a step touches (both
+        # population copies, history, statics; not the FP64 staging planes)
+        # is ~0.8 of it, so these keep a lane's working set near the 256 MB
+        # last-level cache (measured best of 96-320 MiB on a 64-job stream)
+        if lane_bytes is None:
+            lane_bytes = (320 << 20) if storage in ("fp16dev", "bf16dev") else (192 << 20)
+        self.lane_bytes = int(lane_bytes)
+        self.max_members = int(max_members)
+        self.lanes: list = []     # [Batch, bytes resident in it]
+        self.resident: list = []  # [JobResult, Domain, remaining, denominator, mass0, bytes, lane]
         self.used = 0
+
+    def _new_lane(self):
+        kw = dict(storage=self.storage, tile=self.tile, max_members=self.max_members,
+                  max_tiles=self.max_members * (1024 * 1024 // (64 * 4)))
+        if self.lanes:  # every lane on the first lane's stream: lanes run one after another
+            kw["stream"] = self.lanes[0][0].stream
+        self.lanes.append([lbmgls.Batch(**kw), 0])
+        return self.lanes[-1]
+
+    def _lane_for(self, nbytes: int):
+        """The fullest lane the job fits in, else an empty one, else a new one."""
+        fits = [ln for ln in self.lanes if ln[1] + nbytes <= self.lane_bytes]
+        if fits:
+            return max(fits, key=lambda ln: ln[1])
+        empty = [ln for ln in self.lanes if ln[1] == 0]
+        return empty[0] if empty else self._new_lane()
 
     def _footprint(self, spec: JobSpec) -> int:
         w = spec.workload(**self.overrides)
         return lbmgls.workspace_bytes(w.params, self.storage, self.tile), w
 
     def _admit(self, spec: JobSpec, res: JobResult, w, nbytes: int, now: float):
-        d = self.batch.domain(w.params, *w.arrays(), tile=self.tile)
+        lane = self._lane_for(nbytes)
+        d = lane[0].domain(w.params, *w.arrays(), tile=self.tile)
         m0 = d.mass()
-        self.batch.add(d)
+        lane[0].add(d)
+        lane[1] += nbytes
         self.used += nbytes
         res.admitted = now
-        self.resident.append([res, d, spec.steps, float(np.abs(w.phi).sum()), m0, nbytes])
+        self.resident.append([res, d, spec.steps, float(np.abs(w.phi).sum()), m0, nbytes, lane])
 
     def _retire(self, entry, now: float, status: str):
         res, d = entry[0], entry[1]
@@ -115,7 +146,8 @@ class Server:
                 res.phi = d.read()[0]
         res.status = status
         res.finished = now
-        self.batch.remove(d)
+        entry[6][0].remove(d)
+        entry[6][1] -= entry[5]
         d.close()
         self.used -= entry[5]
         if self.on_retire is not None:
@@ -144,14 +176,22 @@ class Server:
                 if pending and realtime:
                     time.sleep(max(0.0, min(0.01, pending[0].arrival_s - now)))
                 continue
-            budget = [e[2] for e in self.resident]
-            n = min(self.tick, max(budget))
-            self.batch.step(n, budget=budget)
+            steps = {}
+            for lane in self.lanes:
+                # the lane's members in their order in the batch (admission order)
+                members = [e for e in self.resident if e[6] is lane]
+                if not members:
+                    continue
+                budget = [e[2] for e in members]
+                n = min(self.tick, max(budget))
+                lane[0].step(n, budget=budget)
+                ticks += 1
+                for e in members:
+                    steps[id(e)] = min(n, e[2])
             _sync()
-            ticks += 1
             now = time.perf_counter() - t0
             for e in list(self.resident):
-                e[2] -= min(n, e[2])
+                e[2] -= steps[id(e)]
                 if not e[1].check():
                     self._retire(e, now, "failed")
                     self.resident.remove(e)
@@ -163,10 +203,12 @@ class Server:
 
     def close(self):
         for e in self.resident:
-            self.batch.remove(e[1])
+            e[6][0].remove(e[1])
             e[1].close()
         self.resident.clear()
-        self.batch.close()
+        for lane in self.lanes:
+            lane[0].close()
+        self.lanes.clear()
 
 
 def run_solo(jobs: list[JobSpec], storage: str = "fp32", tile: int = 0, check_every: int = 1000,

@@ -48,13 +48,18 @@ class FakeBatch:
     def __init__(self, lib, **kw):
         self.lib = lib
         self.members = []
+        self.stream = kw.get("stream", object())  # lanes after the first share its stream
+        self.lane_peak = 0
+        lib.batches.append(self)
 
     def domain(self, params, *arrays, tile=0):
         return FakeDomain(self.lib, params, *arrays)
 
     def add(self, d):
         self.members.append(d)
-        used = sum(self.lib.footprint(m.side) for m in self.members)
+        lane = sum(self.lib.footprint(m.side) for m in self.members)
+        self.lane_peak = max(self.lane_peak, lane)
+        used = sum(self.lib.footprint(m.side) for b in self.lib.batches for m in b.members)
         self.lib.peak = max(self.lib.peak, used)
         self.lib.order.append(d.side)
 
@@ -78,6 +83,7 @@ class FakeLib:
         self.peak = 0
         self.ticks = 0
         self.order = []
+        self.batches = []
 
     @staticmethod
     def footprint(side):
@@ -148,3 +154,24 @@ def test_solo_path_reports_failures_and_steps(fake):
     assert by[3].status == "failed"
     assert all(by[j.job_id].status == "done" and np.all(by[j.job_id].phi == j.steps)
                for j in jobs if j.job_id != 3)
+
+
+def test_server_packs_jobs_into_cache_sized_lanes(fake):
+    """Lanes hold at most lane_bytes of workspaces (a larger job gets a lane of
+    its own), a job goes to the fullest lane it fits, all lanes share the first
+    lane's stream, and every job still gets exactly its step budget."""
+    jobs = stream()
+    lane = FakeLib.footprint(128) + FakeLib.footprint(64)
+    srv = serve.Server(storage="fp32", budget_bytes=10 * FakeLib.footprint(192), tick_steps=100, tile=8,
+                       keep_phi=True, lane_bytes=lane)
+    st = srv.run(jobs, realtime=False)
+    srv.close()
+    assert len(fake.batches) >= 3
+    assert all(b.stream is fake.batches[0].stream for b in fake.batches)
+    for b in fake.batches:
+        assert b.lane_peak <= lane or b.lane_peak == FakeLib.footprint(192)
+    by = {j.job_id: j for j in st.jobs}
+    for j in jobs:
+        if j.job_id != 3:
+            assert by[j.job_id].status == "done" and np.all(by[j.job_id].phi == j.steps)
+    assert st.summary()["ticks"] == fake.ticks
