@@ -1027,41 +1027,33 @@ __global__ __launch_bounds__(PT_NT) void k_part_static(const double* __restrict_
     constexpr int HW = PT_X + 2, HH = PT_Y + 2;
     constexpr int NWV = PT_NT / 64;
     __shared__ int list[PT_MAXLIST];
-    __shared__ int wcnt[NWV];
     __shared__ int cnt;
     __shared__ double spsi[HH * HW];
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int ntx = (nx + PT_X - 1) / PT_X;
     const int x0 = (int)(blockIdx.x % ntx) * PT_X, y0 = (int)(blockIdx.x / ntx) * PT_Y;
     const double cx = x0 + 0.5 * (PT_X - 1), cy = y0 + 0.5 * (PT_Y - 1);
-    if (tid == 0) cnt = 0;
-    __syncthreads();
-    // candidate list in index order: ballot per wave, prefix over the waves,
-    // one chunk of PT_NT particles at a time
-    for (int k0 = 0; k0 < np; k0 += PT_NT) {
-        const int k = k0 + tid;
-        bool h = false;
-        if (k < np) {
-            const double* q = parts + k * PSTRIDE;
-            const double reach = q[PRAD] + PCUT * D + 1.0;  // + the halo of the Laplacian
-            const double dx = fabs(perdw(cx - q[PX], nx, walls & 2)), dy = fabs(perdw(cy - q[PY], ny, walls & 1));
-            h = dx <= 0.5 * PT_X + reach && dy <= 0.5 * PT_Y + reach;
+    // candidate list in index order, built by the first wave alone (ballot
+    // over 64 particles at a time), then one barrier
+    if (wv == 0) {
+        int c = 0;
+        for (int k0 = 0; k0 < np; k0 += 64) {
+            const int k = k0 + lane;
+            bool h = false;
+            if (k < np) {
+                const double* q = parts + k * PSTRIDE;
+                const double reach = q[PRAD] + PCUT * D + 1.0;  // + the halo of the Laplacian
+                const double dx = fabs(perdw(cx - q[PX], nx, walls & 2)), dy = fabs(perdw(cy - q[PY], ny, walls & 1));
+                h = dx <= 0.5 * PT_X + reach && dy <= 0.5 * PT_Y + reach;
+            }
+            const unsigned long long m = __ballot(h);
+            const int pos = c + __popcll(m & ((1ull << lane) - 1ull));
+            if (h && pos < PT_MAXLIST) list[pos] = k;
+            c += __popcll(m);
         }
-        const unsigned long long m = __ballot(h);
-        if (lane == 0) wcnt[wv] = __popcll(m);
-        __syncthreads();
-        int before = cnt;
-        for (int w = 0; w < wv; ++w) before += wcnt[w];
-        const int pos = before + __popcll(m & ((1ull << lane) - 1ull));
-        if (h && pos < PT_MAXLIST) list[pos] = k;
-        __syncthreads();
-        if (tid == 0) {
-            int t = cnt;
-            for (int w = 0; w < NWV; ++w) t += wcnt[w];
-            cnt = t < PT_MAXLIST ? t : PT_MAXLIST;
-        }
-        __syncthreads();
+        if (lane == 0) cnt = c < PT_MAXLIST ? c : PT_MAXLIST;
     }
+    __syncthreads();
     const unsigned char was = touched[blockIdx.x];
     if (cnt == 0 && !was) return;  // uniform: nothing here changed
     for (int i = tid; i < HH * HW; i += PT_NT) {
