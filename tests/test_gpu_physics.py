@@ -173,3 +173,21 @@ def test_sedimentation_in_a_stratified_channel(gpu):
     assert 2.6 < late[:, 1].min() and late[:, 1].max() < 2.9 and np.abs(late[:, 2]).max() < 0.1
     # it did reach the interface first (the fall is stopped, then oscillates)
     assert h[:, 2].max() > 1.0
+
+
+@pytest.mark.parametrize("R,n", [(16, 96), (32, 160), (64, 288)])
+def test_laplace_law_gpu(gpu, R, n):
+    """Static drop (2-D): the pressure jump equals sigma / R (the Laplace law),
+    measured at density ratio 10 on grids the oracle would take hours for;
+    the drop stays at rest (spurious currents < 1e-5)."""
+    w = W.static_drop(n=n, R=R, sigma=1e-2, M=0.1, mu1=0.3, mu2=0.3, rho2=0.1)
+    d = gpu.Domain(w.params, *w.arrays(), storage="fp64")
+    d.step(int(6 * n * n / 100) + 4000)
+    phi, ux, uy, P = d.read()
+    c = int(round(w.meta["centre"]))
+    dp = P[c - 2:c + 3, c - 2:c + 3].mean() - P[:3, :3].mean()
+    r_eff = math.sqrt(((phi + 1) / 2).sum() / math.pi)
+    ratio = dp / (w.params["sigma"] / r_eff)
+    print(f"\nLaplace R={R}: dp / (sigma/R) = {ratio:.4f}")
+    assert abs(ratio - 1) < 0.03
+    assert np.abs(ux).max() < 1e-5 and np.abs(uy).max() < 1e-5
