@@ -7,6 +7,8 @@ import pytest
 
 from paper_2311_05097_amd import workloads as W
 
+from capfit import cap_angle, cap_state
+
 pytestmark = pytest.mark.gpu
 
 
@@ -191,3 +193,37 @@ def test_laplace_law_gpu(gpu, R, n):
     print(f"\nLaplace R={R}: dp / (sigma/R) = {ratio:.4f}")
     assert abs(ratio - 1) < 0.03
     assert np.abs(ux).max() < 1e-5 and np.abs(uy).max() < 1e-5
+
+
+@pytest.mark.parametrize("theta", [30.0, 60.0, 120.0, 150.0])
+def test_young_angle_large_drop(gpu, theta):
+    """Young's law on a flat diffuse wall (Sec. 2.1) for a drop ten interface
+    widths across (R0 = 40 on 320 x 160), FP64: a cap of angle theta given
+    theta keeps it within 2.5 degrees over 20000 steps on the whole range
+    from hydrophilic to hydrophobic (the oracle's own pin, on a drop of radius
+    12, needs 4 degrees)."""
+    ys = 15.5
+    w, phi = cap_state(320, 160, ys, 40.0, theta, theta)
+    d = gpu.Domain(w.params, phi, w.phi0, w.cos_theta, storage="fp64")
+    d.step(20000)
+    got = cap_angle(d.read()[0], ys)
+    print(f"\nYoung theta={theta}: {got:.2f}")
+    assert abs(got - theta) < 2.5, got
+
+
+@pytest.mark.parametrize("theta", [45.0, 135.0])
+def test_contact_line_relaxes_to_young(gpu, theta):
+    """A 90-degree cap given theta = 45 or 135 degrees moves its contact line
+    until the angle approaches theta (R0 = 32 on 256 x 128, FP64): the angle
+    goes monotonically toward theta and ends within 4 degrees of it."""
+    ys = 15.5
+    w, phi = cap_state(256, 128, ys, 32.0, theta, 90.0)
+    d = gpu.Domain(w.params, phi, w.phi0, w.cos_theta, storage="fp64")
+    seen = []
+    for s in (20000, 40000, 60000):
+        d.step(s)
+        seen.append(cap_angle(d.read()[0], ys))
+    print(f"\nrelaxation to {theta}: {[round(a, 2) for a in seen]}")
+    gaps = [abs(a - theta) for a in [90.0] + seen]
+    assert all(b < a for a, b in zip(gaps, gaps[1:])), seen
+    assert gaps[-1] < 4.0, seen
