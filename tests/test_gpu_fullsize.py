@@ -1,0 +1,104 @@
+"""Parity with the FP64 oracle at the full sizes of the benchmark's other
+workloads, in the tile shapes it times them with:
+
+* the cylinder + drop physics on 4096 x 4096 (working set far above the
+  last-level cache), FP64 with 64 x 8 tiles and FP32 with 64 x 16 tiles,
+  over the first 2 steps (the second carries the explicit-Euler time
+  derivatives and the lagged velocity of the first);
+* the 1024 x 2048 gas-liquid pool with 64 free particles, FP64, FP32 and
+  FP16-dev storage with 64 x 8 tiles, over 3 steps, fields and particle
+  state; tiles of 4, 8 and 16 rows give bitwise the same result there.
+
+Bars as in the small-size parity tests: FP64 <= 1e-12 relative, FP32 <= 1e-5
+relative on phi and P, FP16-dev within its storage quantisation.  The oracle
+runs once per workload (about a minute for 4096 x 4096 on 16 threads, 11 GB
+of host memory).
+"""
+import numpy as np
+import pytest
+
+from paper_2311_05097_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def gpu():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2311_05097_amd import lbmgls
+    lbmgls.lib()
+    return lbmgls
+
+
+def rel(a, b):
+    n = np.linalg.norm(b)
+    return float(np.linalg.norm(a - b) / n) if n > 0 else float(np.linalg.norm(a - b))
+
+
+@pytest.fixture(scope="module")
+def r4096():
+    from oracle.oracle import Oracle
+    w = W.roofline_grid()
+    o = Oracle(w.params, *w.arrays())
+    o.step(2)
+    out = o.read()
+    del o
+    return w, out
+
+
+@pytest.mark.parametrize("storage,tile,tol", [("fp64", 8, 1e-12), ("fp32", 16, 1e-5)])
+def test_r4096_full_size(gpu, r4096, storage, tile, tol):
+    w, ref = r4096
+    d = gpu.Domain(w.params, *w.arrays(), storage=storage, tile=tile)
+    d.step(2)
+    errs = {n: rel(a, b) for n, a, b in zip(("phi", "ux", "uy", "P"), d.read(), ref)}
+    print(f"\n4096^2 {storage} 64x{tile} 2 steps: " + " ".join(f"{k}={v:.2e}" for k, v in errs.items()))
+    names = ("phi", "ux", "uy", "P") if storage == "fp64" else ("phi", "P")
+    for k in names:
+        assert errs[k] <= tol, (k, errs[k])
+
+
+@pytest.fixture(scope="module")
+def c5():
+    from oracle.oracle import Oracle
+    w = W.pool_with_particles()
+    o = Oracle(w.params, *w.arrays(), particles=w.particles)
+    o.step(3)
+    return w, o.read(), o.particles()
+
+
+def _c5_run(gpu, w, storage, tile):
+    d = gpu.Domain(w.params, *w.arrays(), storage=storage, tile=tile, particles=w.particles)
+    d.step(3)
+    return d.read(), d.particles()
+
+
+@pytest.mark.parametrize("storage", ["fp64", "fp32", "fp16dev"])
+def test_c5_full_size(gpu, c5, storage):
+    w, ref, (os_, oo) = c5
+    assert len(w.particles) == 64
+    fields, (ds, do) = _c5_run(gpu, w, storage, 8)
+    errs = {n: rel(a, b) for n, a, b in zip(("phi", "ux", "uy", "P"), fields, ref)}
+    perr = float(np.abs(ds - os_).max())
+    ferr = float(np.abs(do[:, :3] - oo[:, :3]).max() / np.abs(oo[:, :3]).max())
+    print(f"\nC5 {storage} 64x8 3 steps: " + " ".join(f"{k}={v:.2e}" for k, v in errs.items())
+          + f" state={perr:.2e} force={ferr:.2e}")
+    if storage == "fp64":
+        for k, e in errs.items():
+            assert e <= 1e-12, (k, e)
+        assert perr <= 1e-12 and ferr <= 1e-10
+    elif storage == "fp32":
+        assert errs["phi"] <= 1e-5 and errs["P"] <= 1e-5
+        assert perr <= 1e-6 and ferr <= 1e-4
+    else:
+        assert errs["phi"] <= 1e-3 and perr <= 1e-4
+
+
+def test_c5_full_size_tiles_bitwise(gpu, c5):
+    w = c5[0]
+    runs = [_c5_run(gpu, w, "fp32", t) for t in (4, 8, 16)]
+    flat = [list(f) + list(p) for f, p in runs]
+    for other in flat[1:]:
+        for a, b in zip(flat[0], other):
+            assert np.array_equal(a, b)
