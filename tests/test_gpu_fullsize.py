@@ -7,12 +7,15 @@ workloads, in the tile shapes it times them with:
   derivatives and the lagged velocity of the first);
 * the 1024 x 2048 gas-liquid pool with 64 free particles, FP64, FP32 and
   FP16-dev storage with 64 x 8 tiles, over 3 steps, fields and particle
-  state; tiles of 4, 8 and 16 rows give bitwise the same result there.
+  state; tiles of 4, 8 and 16 rows give bitwise the same result there;
+* the 1024 x 1024 cylinder + drop geometry between bounce-back walls,
+  FP64 and FP32, over 3 steps;
+* the 4096 x 4096 voxel-solid smoothing (20 Cahn-Hilliard steps).
 
 Bars as in the small-size parity tests: FP64 <= 1e-12 relative, FP32 <= 1e-5
 relative on phi and P, FP16-dev within its storage quantisation.  The oracle
-runs once per workload (about a minute for 4096 x 4096 on 16 threads, 11 GB
-of host memory).
+runs once per workload (about a minute for the 4096 x 4096 step on 16
+threads, 11 GB of host memory, and a minute for the smoothing).
 """
 import numpy as np
 import pytest
@@ -102,3 +105,35 @@ def test_c5_full_size_tiles_bitwise(gpu, c5):
     for other in flat[1:]:
         for a, b in zip(flat[0], other):
             assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("storage,tile,tol", [("fp64", 8, 1e-12), ("fp32", 8, 1e-5), ("fp32", 4, 1e-5)])
+def test_c2_channel_walls_full_size(gpu, storage, tile, tol):
+    """The 1024 x 1024 cylinder + drop geometry closed by bounce-back walls
+    below and above (no gravity, mu1 = 0.3, viscosity ratio 50: the walled
+    case the benchmark times), 3 steps against the oracle."""
+    from oracle.oracle import Oracle
+    w = W.cylinder_drop(1024, 128.0, 160.0, g=0.0)
+    w.params.update(mu1=0.3, mu2=0.3 / 50, bounce_y=1)
+    o = Oracle(w.params, *w.arrays())
+    o.step(3)
+    d = gpu.Domain(w.params, *w.arrays(), storage=storage, tile=tile)
+    d.step(3)
+    errs = {n: rel(a, b) for n, a, b in zip(("phi", "ux", "uy", "P"), d.read(), o.read())}
+    print(f"\nC2 channel {storage} 64x{tile} 3 steps: " + " ".join(f"{k}={v:.2e}" for k, v in errs.items()))
+    names = ("phi", "ux", "uy", "P") if storage == "fp64" else ("phi", "P")
+    for k in names:
+        assert errs[k] <= tol, (k, errs[k])
+
+
+def test_voxel_smoothing_full_size(gpu):
+    """The 4096 x 4096 voxel solid of 3000 grains smoothed by 20
+    Cahn-Hilliard steps, as timed by the benchmark, against the oracle."""
+    from oracle import oracle as O
+    s = W.voxel_solid(4096, 4096, n_grains=3000, seed=9, r_range=(6.0, 30.0))
+    p = W.params(4096, 4096)
+    g = gpu.smooth_solid(p, s, 20)
+    o = O.smooth_solid(s, p["D"], 20)
+    err = float(np.abs(g - o).max())
+    print(f"\nvoxel smoothing 4096^2: max abs diff {err:.2e}")
+    assert err <= 1e-13
