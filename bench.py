@@ -253,10 +253,11 @@ def main():
     ap.add_argument("--no-extra", action="store_true")
     ap.add_argument("--no-serve", action="store_true", help="skip the served-jobs leg of the default run")
     ap.add_argument("--copy-calibrate", action="store_true")
-    ap.add_argument("--workload", default="c2", choices=["c2", "r4096", "c5"],
+    ap.add_argument("--workload", default="c2", choices=["c2", "r4096", "c5", "c3"],
                     help="c2: the 1024^2 cylinder + drop case (default); r4096: the same physics "
                          "on 4096^2 (working set far above the last-level cache); c5: the 1024 x 2048 "
-                         "pool with 64 free particles (step time includes the particle kernels)")
+                         "pool with 64 free particles (step time includes the particle kernels); c3: the "
+                         "2048 x 1024 porous channel with 200 obstacles")
     ap.add_argument("--walls", default="none", choices=["none", "y", "box"],
                     help="close the workload with no-flux bounce-back walls: below and above (y) or on "
                          "all four sides (box)")
@@ -288,7 +289,8 @@ def main():
 
     from paper_2311_05097_amd import workloads as W
     from paper_2311_05097_amd import autotune
-    w = {"c2": W.config2, "r4096": W.roofline_grid, "c5": W.pool_with_particles}[args.workload]()
+    w = {"c2": W.config2, "r4096": W.roofline_grid, "c5": W.pool_with_particles,
+         "c3": W.config3}[args.workload]()
     if args.walls != "none":
         w.params.update(bounce_y=1, bounce_x=1 if args.walls == "box" else 0)
     R = W.roofline_grid()
@@ -362,6 +364,15 @@ def main():
         extra["C2_walls_fp32"] = {"mlups": round(e["mlups"], 1), "tile": t, "bounce_y": 1,
                                   "roofline": roofline("fp32", e["nodes"], e["kernel_ms"]),
                                   "mass_drift": e["mass_drift"], "finite": e["finite"]}
+        # the porous channel: 2048 x 1024, diffuse channel walls, 200 circular
+        # obstacles with contact angles U[45, 135] degrees (a per-node
+        # cos theta field), density ratio 1000, body force along x
+        C3 = W.config3()
+        t = autotune.best_tile(C3.params, "fp32")
+        e = run_gpu(C3, "fp32", 2000, 100, t)
+        extra["C3_fp32"] = {"mlups": round(e["mlups"], 1), "tile": t, "obstacles": len(C3.meta["circles"]),
+                            "roofline": roofline("fp32", e["nodes"], e["kernel_ms"]),
+                            "mass_drift": e["mass_drift"], "finite": e["finite"]}
         for st in ("fp32", "fp16dev", "fp64"):
             t = autotune.best_tile(R.params, st)
             e = run_gpu(R, st, 300, 20, t)

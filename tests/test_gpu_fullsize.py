@@ -10,7 +10,9 @@ workloads, in the tile shapes it times them with:
   state; tiles of 4, 8 and 16 rows give bitwise the same result there;
 * the 1024 x 1024 cylinder + drop geometry between bounce-back walls,
   FP64 and FP32, over 3 steps;
-* the 4096 x 4096 voxel-solid smoothing (20 Cahn-Hilliard steps).
+* the 4096 x 4096 voxel-solid smoothing (20 Cahn-Hilliard steps);
+* the 2048 x 1024 porous channel with 200 obstacles, FP64 and FP32, over
+  3 steps, and its recipe on a small ragged grid over 200 steps.
 
 Bars as in the small-size parity tests: FP64 <= 1e-12 relative, FP32 <= 1e-5
 relative on phi and P, FP16-dev within its storage quantisation.  The oracle
@@ -137,3 +139,44 @@ def test_voxel_smoothing_full_size(gpu):
     err = float(np.abs(g - o).max())
     print(f"\nvoxel smoothing 4096^2: max abs diff {err:.2e}")
     assert err <= 1e-13
+
+
+@pytest.fixture(scope="module")
+def c3():
+    from oracle.oracle import Oracle
+    w = W.config3()
+    o = Oracle(w.params, *w.arrays())
+    o.step(3)
+    return w, o.read()
+
+
+@pytest.mark.parametrize("storage,tile,tol", [("fp64", 8, 1e-12), ("fp32", 8, 1e-5), ("fp32", 16, 1e-5)])
+def test_c3_porous_channel_full_size(gpu, c3, storage, tile, tol):
+    """The 2048 x 1024 porous channel (diffuse channel walls, 200 obstacles
+    with their own contact angles, density ratio 1000, body force along x),
+    3 steps against the oracle."""
+    w, ref = c3
+    assert len(w.meta["circles"]) == 200
+    d = gpu.Domain(w.params, *w.arrays(), storage=storage, tile=tile)
+    d.step(3)
+    errs = {n: rel(a, b) for n, a, b in zip(("phi", "ux", "uy", "P"), d.read(), ref)}
+    print(f"\nC3 {storage} 64x{tile} 3 steps: " + " ".join(f"{k}={v:.2e}" for k, v in errs.items()))
+    names = ("phi", "ux", "uy", "P") if storage == "fp64" else ("phi", "P")
+    for k in names:
+        assert errs[k] <= tol, (k, errs[k])
+
+
+def test_c3_shaped_small_channel_fp64_200_steps(gpu):
+    """The porous-channel recipe on 333 x 150 (ragged in both directions,
+    12 obstacles, density ratio 10 so that it stays finite), 200 steps."""
+    from oracle.oracle import Oracle
+    w = W.porous_channel(nx=333, ny=150, n_obstacles=12, seed=6, r_range=(6.0, 14.0), rho_ratio=10.0,
+                         mu_ratio=1.0)
+    o = Oracle(w.params, *w.arrays())
+    o.step(200)
+    d = gpu.Domain(w.params, *w.arrays(), storage="fp64", tile=8)
+    d.step(200)
+    errs = {n: rel(a, b) for n, a, b in zip(("phi", "ux", "uy", "P"), d.read(), o.read())}
+    print("\nsmall channel fp64 200 steps: " + " ".join(f"{k}={v:.2e}" for k, v in errs.items()))
+    for k, e in errs.items():
+        assert e <= 1e-12, (k, e)
