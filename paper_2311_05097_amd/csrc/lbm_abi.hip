@@ -298,7 +298,7 @@ int launch_tiles_ty(lbm_domain* d, int t) {
 
 // Reductions at the current level; res[0..3] = mass, E_F, E_K, #non-finite.
 template <class S>
-int reduce(lbm_domain* d, bool with_out, double res[NPART], int64_t* imass) {
+int reduce(lbm_domain* d, bool with_out, double res[NPART], int64_t* imass = nullptr) {
     int rc = upload_job<S>(d, 0, with_out);
     if (rc) return rc;
     if ((rc = launch_tiles_ty<S, MODE_OUT>(d, 0))) return rc;
@@ -309,12 +309,15 @@ int reduce(lbm_domain* d, bool with_out, double res[NPART], int64_t* imass) {
                        S::kFix ? (const int64_t*)(d->ws + d->L.off_ipart) : nullptr, d->L.ntiles, r, ir);
     HIPCHK(hipGetLastError());
     double hr[NPART];
-    int64_t hi = 0;
+    int64_t hi[2] = {0, 0};
     HIPCHK(hipMemcpyAsync(hr, r, sizeof hr, hipMemcpyDeviceToHost, d->stream));
-    HIPCHK(hipMemcpyAsync(&hi, ir, sizeof hi, hipMemcpyDeviceToHost, d->stream));
+    HIPCHK(hipMemcpyAsync(hi, ir, sizeof hi, hipMemcpyDeviceToHost, d->stream));
     HIPCHK(hipStreamSynchronize(d->stream));
     for (int k = 0; k < NPART; ++k) res[k] = hr[k];
-    if (imass) *imass = hi;
+    if (imass) {  // normalised: imass[0] 2^32 + imass[1], 0 <= imass[1] < 2^32
+        imass[0] = hi[0] + (hi[1] >> 32);
+        imass[1] = hi[1] & 0xffffffffLL;
+    }
     return LBM_OK;
 }
 
@@ -728,10 +731,12 @@ int lbm_mass(lbm_domain* d, double* sum_phi) {
     return dispatch(d->p.storage, [&](auto s) -> int {
         using S = decltype(s);
         double res[NPART];
-        int64_t im = 0;
-        int r = reduce<S>(d, false, res, &im);
+        int64_t im[2] = {0, 0};
+        int r = reduce<S>(d, false, res, im);
         if (r) return r;
-        *sum_phi = S::kFix ? std::ldexp((double)im, -FIX_BITS) : res[0];
+        // im[0] 2^32 and im[1] are exact doubles (|im[0]| < 2^44, im[1] < 2^32):
+        // their sum is the exact fixed-point mass rounded once
+        *sum_phi = S::kFix ? std::ldexp((double)im[0] * 4294967296.0 + (double)im[1], -FIX_BITS) : res[0];
         return LBM_OK;
     });
 }

@@ -1321,36 +1321,47 @@ __global__ __launch_bounds__(NT) void k_vox(const double* __restrict__ a, const 
     }
 }
 
-// Fixed-order sum of the per-tile partials: res[k] = sum_i part[i][k],
-// res[NPART] = exact fixed-point mass (16-bit modes) as a double-rounded value
-// and ires[0] its 64-bit integer.
+// Fixed-order sum of the per-tile partials: res[k] = sum_i part[i][k], and
+// (16-bit modes) the exact fixed-point mass as two 64-bit integers, ires[0]
+// the sum of the tiles' upper halves (v >> 32) and ires[1] the sum of their
+// lower 32 bits, so that mass = ires[0] 2^32 + ires[1] in units of 2^-40.
+// A tile's partial is below 2^51 in magnitude; a single 64-bit total would
+// wrap once |sum phi| passes 2^23, while the halves stay below 2^44 and 2^57
+// for every domain of fewer than 2^31 nodes.
 __global__ __launch_bounds__(NT) void k_final_sum(const double* __restrict__ part,
                                                   const int64_t* __restrict__ ipart, int ntiles,
                                                   double* __restrict__ res, int64_t* __restrict__ ires) {
     __shared__ double s[NT][NPART];
-    __shared__ long long si[NT];
+    __shared__ long long si[NT][2];
     double acc[NPART] = {0.0, 0.0, 0.0, 0.0};
-    long long ai = 0;
+    long long ah = 0, al = 0;
     for (int i = threadIdx.x; i < ntiles; i += NT) {
 #pragma unroll
         for (int k = 0; k < NPART; ++k) acc[k] += part[(int64_t)i * NPART + k];
-        if (ipart) ai += ipart[i];
+        if (ipart) {
+            const long long v = ipart[i];
+            ah += v >> 32;
+            al += v & 0xffffffffLL;
+        }
     }
 #pragma unroll
     for (int k = 0; k < NPART; ++k) s[threadIdx.x][k] = acc[k];
-    si[threadIdx.x] = ai;
+    si[threadIdx.x][0] = ah;
+    si[threadIdx.x][1] = al;
     __syncthreads();
     for (int h = NT / 2; h > 0; h >>= 1) {
         if ((int)threadIdx.x < h) {
 #pragma unroll
             for (int k = 0; k < NPART; ++k) s[threadIdx.x][k] += s[threadIdx.x + h][k];
-            si[threadIdx.x] += si[threadIdx.x + h];
+            si[threadIdx.x][0] += si[threadIdx.x + h][0];
+            si[threadIdx.x][1] += si[threadIdx.x + h][1];
         }
         __syncthreads();
     }
     if (threadIdx.x == 0) {
         for (int k = 0; k < NPART; ++k) res[k] = s[0][k];
-        ires[0] = si[0];
+        ires[0] = si[0][0];
+        ires[1] = si[0][1];
     }
 }
 

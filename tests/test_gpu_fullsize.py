@@ -180,3 +180,35 @@ def test_c3_shaped_small_channel_fp64_200_steps(gpu):
     print("\nsmall channel fp64 200 steps: " + " ".join(f"{k}={v:.2e}" for k, v in errs.items()))
     for k, e in errs.items():
         assert e <= 1e-12, (k, e)
+
+
+@pytest.mark.parametrize("storage", ["fp16dev", "fp32"])
+def test_large_domain_is_the_small_one_tiled(gpu, storage):
+    """A periodic 16384 x 16384 domain (2^28 nodes: every population plane
+    and offset past 4 GiB) started from the 1024 x 1024 cylinder + drop state
+    repeated 16 x 16 times is the 1024 x 1024 problem: after 5 steps its
+    fields are that problem's fields repeated, bit for bit, and in the 16-bit
+    mode its exact phase mass is 256 times the small domain's."""
+    import gc
+    w = W.cylinder_drop(1024, 128.0, 160.0, g=0.0)
+    w.params.update(mu1=0.3, mu2=0.3 / 50)
+    small = gpu.Domain(w.params, *w.arrays(), storage=storage, tile=8)
+    small.step(5)
+    ref = small.read()
+    m_small = small.mass()
+    small.close()
+    k = 16
+    pl = dict(w.params, nx=1024 * k, ny=1024 * k)
+    big = gpu.Domain(pl, *[np.tile(a, (k, k)) for a in w.arrays()], storage=storage, tile=8)
+    gc.collect()
+    big.step(5)
+    m_big = big.mass()
+    got = big.read()
+    big.close()
+    for a, b in zip(got, ref):
+        assert a.shape == (1024 * k, 1024 * k)
+        assert np.array_equal(a.reshape(k, 1024, k, 1024), np.broadcast_to(b[None, :, None, :], (k, 1024, k, 1024)))
+    if storage == "fp16dev":
+        assert m_big == 256.0 * m_small
+    else:
+        assert abs(m_big - 256.0 * m_small) <= 1e-9 * abs(256.0 * m_small) + 1e-6
