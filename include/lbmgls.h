@@ -197,8 +197,10 @@ int lbm_check(lbm_domain *d);
  * each nx*ny doubles; any pointer may be NULL.  Blocks. */
 int lbm_read(lbm_domain *d, double *phi, double *ux, double *uy, double *p);
 
-/* Total order parameter sum phi (FP64 reduction in a fixed order; exact
- * 64-bit integer sum for the *DEV storage modes).  Blocks. */
+/* Total order parameter sum phi (FP64 reduction in a fixed order; for the
+ * *DEV storage modes the exact fixed-point sum, in units of 2^-40, carried
+ * without overflow for every domain size and rounded once to a double).
+ * Blocks. */
 int lbm_mass(lbm_domain *d, double *sum_phi);
 
 /* Discrete free energy E_F of Eq. (2energy) (wetting terms through
