@@ -233,3 +233,17 @@ def test_contact_angle_moves_toward_young(orc):
     angle."""
     got = _cap_run(orc, 90.0, 60.0)
     assert got > 64.0, got
+
+
+@pytest.mark.parametrize("theta", [30.0, 60.0, 90.0, 120.0, 150.0])
+def test_cap_fit_recovers_a_known_angle(theta):
+    """The contact-angle measurement itself: on a drawn diffuse circular cap
+    that meets the wall line y = ys at a known angle, the circle fit through
+    the phi = 0 crossings returns that angle within 0.2 degrees."""
+    nx, ny, ys, D = 320, 160, 15.5, 4.0
+    t = math.radians(theta)
+    Rc = 40.0 / math.sqrt(max(t - math.sin(t) * math.cos(t), 1e-9) / (0.5 * math.pi))
+    yc = ys - Rc * math.cos(t)
+    y, x = np.mgrid[0:ny, 0:nx].astype(float)
+    phi = np.tanh((Rc - np.hypot(x - nx / 2, y - yc)) / (D / 2))
+    assert abs(cap_angle(phi, ys) - theta) < 0.2
