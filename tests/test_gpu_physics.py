@@ -227,3 +227,21 @@ def test_contact_line_relaxes_to_young(gpu, theta):
     gaps = [abs(a - theta) for a in [90.0] + seen]
     assert all(b < a for a, b in zip(gaps, gaps[1:])), seen
     assert gaps[-1] < 4.0, seen
+
+
+@pytest.mark.parametrize("storage", ["fp32", "fp16dev", "bf16dev"])
+def test_young_angle_reduced_precision(gpu, storage):
+    """The large-drop Young test in the reduced-precision storage modes: a
+    120-degree cap given 120 degrees ends within 2.5 degrees of it and within
+    0.5 degrees of the FP64 run after 20000 steps."""
+    ys = 15.5
+    w, phi = cap_state(320, 160, ys, 40.0, 120.0, 120.0)
+    got = {}
+    for st in ("fp64", storage):
+        d = gpu.Domain(w.params, phi, w.phi0, w.cos_theta, storage=st)
+        d.step(20000)
+        got[st] = cap_angle(d.read()[0], ys)
+        d.close()
+    print(f"\nYoung 120 {storage}: {got[storage]:.2f} (fp64 {got['fp64']:.2f})")
+    assert abs(got[storage] - 120.0) < 2.5
+    assert abs(got[storage] - got["fp64"]) < 0.5
