@@ -98,6 +98,14 @@ typedef struct {
        the channel of Sec. 4.5); at a corner a population that would leave
        through either wall returns to its node. */
     int32_t bounce_x;
+    /* H of the pressure recovery (Sec. 3.2, after Eq. u).  0: the factor that
+       the first-order non-equilibrium moments of this model give,
+       H = -K (1 - 3 d0) (1/s2a - 1/2) (default; with it a planar interface
+       translating at a uniform speed keeps that speed to the interface's
+       discretisation error).  1: the factor as printed,
+       K [(1 - d0)/s0 - (2 - 4 d0)/s2a + (1 - 3 d0)/2]; the two differ by
+       K^2 (1/s0 - 1/s2a) and agree when s0 = s2a. */
+    int32_t h_form;
 } lbm_params;
 
 typedef struct lbm_domain lbm_domain;
@@ -130,7 +138,8 @@ int lbm_create(const lbm_params *p, void *dev_workspace, size_t bytes, void *hip
  * particle.  A density <= 0 marks a solid of prescribed motion (e.g. a
  * rotating cylinder): its velocity and angular velocity are held, its centre
  * advances with its velocity, and its force and torque are still reported.  phi0 and cos_theta describe the stationary solid only; each
- * particle adds its tanh indicator (Sec. 4.5, zero from R + 5 D on) and every
+ * particle adds its tanh indicator (Sec. 4.5; every node, as the plain
+ * formula) and every
  * node takes the angle and solid velocity u_p + omega_p x (x - x_p) of the
  * largest indicator component.  After every step except the first, the
  * hydrodynamic force and torque (Eq. Ff) are summed in FP64 over each

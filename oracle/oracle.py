@@ -10,6 +10,7 @@ paper passages it follows and the readings it takes.
 """
 from __future__ import annotations
 
+import contextlib
 import ctypes
 import os
 import subprocess
@@ -49,14 +50,14 @@ class OrcParams(ctypes.Structure):
         ("wall_x0", ctypes.c_double), ("wall_x1", ctypes.c_double),
         ("wall_y0", ctypes.c_double), ("wall_y1", ctypes.c_double),
         ("walls", ctypes.c_int32), ("bounce_y", ctypes.c_int32),
-        ("bounce_x", ctypes.c_int32),
+        ("bounce_x", ctypes.c_int32), ("h_form", ctypes.c_int32),
     ]
 
 
 # parameters of the free-particle extension; absent keys take these values
 OPTIONAL = {"rep_xi": 0.0, "rep_eps": 1.0, "wall_x0": 0.0, "wall_x1": 0.0, "wall_y0": 0.0,
             "wall_y1": 0.0, "walls": 0, "bounce_y": 0,
-            "bounce_x": 0}
+            "bounce_x": 0, "h_form": 0}
 # particle state columns (input) and per-particle outputs of the last update
 PARTICLE_IN = ["x", "y", "ux", "uy", "omega", "R", "rho_p", "cos_theta"]
 PARTICLE_OUT = ["Fx", "Fy", "T", "Fin_x", "Fin_y", "Tin", "rho_in"]
@@ -113,6 +114,8 @@ def lib():
         L.orc_lap.argtypes = [ctypes.c_int, ctypes.c_int, _D, _D]
         L.orc_mu.argtypes = [ctypes.POINTER(OrcParams), _D, _D, _D, _D]
         L.orc_threads.restype = ctypes.c_int
+        L.orc_plant.argtypes = [ctypes.c_int, ctypes.c_double]
+        L.orc_plant.restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -130,6 +133,25 @@ def make_params(p: dict) -> OrcParams:
     for name, _ in OrcParams._fields_:
         setattr(op, name, p[name] if name in p else OPTIONAL[name])
     return op
+
+
+# terms a test may scale to plant a mistake (names of the PL_* factors in
+# lbm_oracle.c, in order)
+PLANT_TERMS = ["H", "KDT", "G", "FC", "FEQS", "M2FDT", "M2FUF", "M2FD0", "M2FISO", "UDR"]
+
+
+@contextlib.contextmanager
+def planted(**factors):
+    """Run the enclosed oracle steps with some terms of the method scaled
+    (e.g. ``planted(FC=-1.0)`` flips the sign of F_c), to show that a pin
+    fails on that mistake.  Every factor is restored to 1 on exit."""
+    L = lib()
+    try:
+        for name, v in factors.items():
+            assert L.orc_plant(PLANT_TERMS.index(name), float(v)) == 0
+        yield
+    finally:
+        L.orc_plant_reset()
 
 
 def threads() -> int:

@@ -109,6 +109,7 @@ int validate(const lbm_params* p) {
     if (p->walls < 0 || p->walls > 15) return fail(LBM_EINVAL, "walls must lie in 0..15");
     if (p->bounce_y != 0 && p->bounce_y != 1) return fail(LBM_EINVAL, "bounce_y must be 0 or 1");
     if (p->bounce_x != 0 && p->bounce_x != 1) return fail(LBM_EINVAL, "bounce_x must be 0 or 1");
+    if (p->h_form != 0 && p->h_form != 1) return fail(LBM_EINVAL, "h_form must be 0 or 1");
     return LBM_OK;
 }
 
@@ -179,8 +180,13 @@ void fill_coef(const lbm_params& p, Coef<R>& c) {
     c.Pw0 = (R)(w0 / one_a);
     const double K = 1.0 - a;
     c.K2 = (R)(K / 2.0);
-    c.Hc0 = (R)(K * (one_a / p.s0 + (1.0 - 3.0 * a) / 2.0));
-    c.Hc1 = (R)(K * (2.0 - 4.0 * a));
+    if (p.h_form == 1) {  // as printed: K [(1 - d0)/s0 - (2 - 4 d0) tau_a + (1 - 3 d0)/2]
+        c.Hc0 = (R)(K * (one_a / p.s0 + (1.0 - 3.0 * a) / 2.0));
+        c.Hc1 = (R)(K * (2.0 - 4.0 * a));
+    } else {              // first-order moments: -K (1 - 3 d0)(tau_a - 1/2)
+        c.Hc0 = (R)(K * (1.0 - 3.0 * a) / 2.0);
+        c.Hc1 = (R)(K * (1.0 - 3.0 * a));
+    }
     // 16-bit modes: power-of-two scales that bring the typical magnitude of
     // the moving phase-field populations (w1 eta 3 sigma / D) and of the flow
     // populations (pressure scale) to about one.

@@ -16,7 +16,8 @@
 // populations, a 3-node halo of the order parameter that neighbouring tiles
 // are updating in the same launch; an in-place (single-copy) update would race.
 //
-// Per step, one launch over 64 x TY tiles (256 threads = 4 wavefronts):
+// Per step, one launch over 64 x TY tiles (64 x 4 tiles: 256 threads = 4
+// wavefronts; taller tiles: 512 threads = 8 wavefronts, TileCfg):
 //   A  phi = sum_i g_i on the tile plus a 3-node halo -> LDS
 //   B  mu (Eq. potential) on tile + 2                 -> LDS
 //   C  S = M (rho1-rho2)/2 grad mu and w = (S x u^{n-1})_z / 2 on tile + 1 -> LDS
@@ -160,7 +161,11 @@ struct Job {
 // carried to the next update (Eq. Ffin), internal fluid density.
 enum { PX, PY, PUX, PUY, POM, PRAD, PRHO, PCOS, PSTRIDE };
 enum { QFX, QFY, QT, QFINX, QFINY, QTIN, QRHOIN, QSTRIDE };
-constexpr double PCUT = 5.0;  // a particle's indicator is 0 from R + PCUT * D on
+// A particle's indicator [1 + tanh(2 (R - r) / D)] / 2 is exactly 0 in FP64
+// from r = R + 9.53 D on (tanh rounds to -1 below -19.06) and in FP32 from
+// R + 4.6 D on, so skipping nodes beyond R + PCUT D changes no value: the
+// indicator equals the plain tanh profile at every node.
+constexpr double PCUT = 10.0;
 
 // ------------------------------------------------------------------ helpers
 // nearest periodic image of a coordinate difference (the division only when

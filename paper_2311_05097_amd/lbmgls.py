@@ -51,7 +51,7 @@ class LbmParams(ctypes.Structure):
         ("wall_x0", ctypes.c_double), ("wall_x1", ctypes.c_double),
         ("wall_y0", ctypes.c_double), ("wall_y1", ctypes.c_double),
         ("np", ctypes.c_int32), ("walls", ctypes.c_int32), ("bounce_y", ctypes.c_int32),
-        ("bounce_x", ctypes.c_int32),
+        ("bounce_x", ctypes.c_int32), ("h_form", ctypes.c_int32),
     ]
 
 

@@ -34,6 +34,9 @@ PAPER_DEFAULTS = dict(
     # no-flux (bounce-back) walls below the first and above the last row,
     # left of the first and right of the last column
     bounce_y=0, bounce_x=0,
+    # H of the pressure recovery: 0 from the model's first-order moments,
+    # 1 as printed (Sec. 3.2, after Eq. u)
+    h_form=0,
 )
 
 # Columns of a particle array: centre, translational and angular velocity,

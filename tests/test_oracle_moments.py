@@ -136,9 +136,13 @@ def test_viscous_rates(orc):
             nu = muv / (rho * (1 - z))
             assert np.isclose((1 / r["s2a"] - 0.5) * (1 - d0) / 2, nu, rtol=1e-13)
             assert np.isclose((1 / r["s2b"] - 0.5) * d0, nu, rtol=1e-13)
+            # H: the factor of the first-order moments (its pin is the
+            # translating interface), and the printed one when asked for
             K = 1 - d0
-            H = K * ((1 - d0) / p["s0"] - (2 - 4 * d0) / r["s2a"] + (1 - 3 * d0) / 2)
-            assert np.isclose(r["H"], H, rtol=1e-13)
+            assert np.isclose(r["H"], -K * (1 - 3 * d0) * (1 / r["s2a"] - 0.5), rtol=1e-13, atol=1e-15)
+            rp = orc.macro_node(dict(p, h_form=1), f, rho, muv, z, 0, 0, 0, 0, 0, 0, 0)
+            Hp = K * ((1 - d0) / p["s0"] - (2 - 4 * d0) / r["s2a"] + (1 - 3 * d0) / 2)
+            assert np.isclose(rp["H"], Hp, rtol=1e-13)
         # in the solid core 1 - phi0 is floored at solid_eps (finite H)
         r = orc.macro_node(p, f, 0.5, 0.1, 1.0, 0, 0, 0, 0, 0, 0, 0)
         nu = 0.1 / (0.5 * p["solid_eps"])

@@ -21,14 +21,13 @@ def _oracle(orc, w):
     return orc.Oracle(w.params, *w.arrays(), particles=w.particles)
 
 
-def _disk(n, xc, yc, R, D, cut=5.0):
-    """Indicator of a disk with the nearest periodic image, zero from
-    R + cut*D on."""
+def _disk(n, xc, yc, R, D):
+    """Indicator of a disk with the nearest periodic image, at every node."""
     y, x = np.mgrid[0:n, 0:n].astype(float)
     dx = (x - xc + n / 2) % n - n / 2
     dy = (y - yc + n / 2) % n - n / 2
     r = np.hypot(dx, dy)
-    return np.where(r < R + cut * D, W.indicator(R - r, D), 0.0)
+    return W.indicator(R - r, D)
 
 
 def test_heavy_particle_is_a_stationary_solid(orc):

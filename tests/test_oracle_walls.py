@@ -128,12 +128,13 @@ def test_particles_see_no_image_through_the_walls(orc):
     """With walls the particle indicator and owner use the distance in y
     without the periodic image: a particle at the lower wall leaves the top
     rows untouched; in the periodic domain its image reaches them."""
-    nx, ny = 40, 30
+    nx, ny = 40, 60
     part = [W.particle(20.0, 3.0, 4.0, 1.0, 90.0)]
     for walls in (1, 0):
         p = W.params(nx, ny, bounce_y=walls)
         o = orc.Oracle(p, np.zeros((ny, nx)), np.zeros((ny, nx)), None, None, None, particles=part)
-        top = o.field("phi0")[-2:]  # beyond the cutoff R + 5 D = 24 from y = 3
+        # more than R + 9.53 D = 42.1 from y = 3: the FP64 indicator is exactly 0
+        top = o.field("phi0")[-2:]
         if walls:
             assert np.all(top == 0.0)
         else:
@@ -192,12 +193,12 @@ def test_closed_box_keeps_its_diagonal_symmetry_and_mass(orc):
 
 
 def test_particles_see_no_image_through_side_walls(orc):
-    nx, ny = 30, 40
+    nx, ny = 60, 40
     part = [W.particle(3.0, 20.0, 4.0, 1.0, 90.0)]
     for walls in (1, 0):
         p = W.params(nx, ny, bounce_x=walls)
         o = orc.Oracle(p, np.zeros((ny, nx)), np.zeros((ny, nx)), None, None, None, particles=part)
-        right = o.field("phi0")[:, -2:]  # beyond the cutoff R + 5 D = 24 from x = 3
+        right = o.field("phi0")[:, -2:]  # more than R + 9.53 D from x = 3: exactly 0
         if walls:
             assert np.all(right == 0.0)
         else:
