@@ -171,8 +171,8 @@ void fill_coef(const lbm_params& p, Coef<R>& c) {
     c.k3s_4D = (R)(3.0 * s / (4.0 * D)); c.k3Ds_16 = (R)(3.0 * D * s / 16.0);
     c.k9s_2D = (R)(9.0 * s / (2.0 * D));
     c.kS = (R)(p.M * (p.rho1 - p.rho2) / 2.0);
-    c.drho = (R)((p.rho1 - p.rho2) / 2.0); c.srho = (R)((p.rho1 + p.rho2) / 2.0);
-    c.dmu = (R)((p.mu1 - p.mu2) / 2.0); c.smu = (R)((p.mu1 + p.mu2) / 2.0);
+    c.drho = (R)((p.rho1 - p.rho2) / 2.0); c.rho2 = (R)p.rho2;
+    c.dmu = (R)((p.mu1 - p.mu2) / 2.0); c.mu2 = (R)p.mu2;
     c.gx = (R)p.gx; c.gy = (R)p.gy; c.rho_ref = (R)p.rho_ref; c.fbx = (R)p.fbx; c.fby = (R)p.fby;
     c.solid_eps = (R)p.solid_eps;
     c.ka = (R)(one_a / 2.0);
@@ -423,8 +423,8 @@ int create_impl(lbm_domain* d, const double* phi, const double* phi0, const doub
         hipLaunchKernelGGL((k_static<R>), dim3(nb), dim3(NT), 0, d->stream,
                            (const double*)(d->ws + L.off_stage), st, L.pitch, N);
         HIPCHK(hipGetLastError());
-        hipLaunchKernelGGL((k_lap_psi<R>), dim3(nb), dim3(NT), 0, d->stream, st, L.pitch, d->p.nx, d->p.ny,
-                           wall_bits(d->p));
+        hipLaunchKernelGGL((k_lap_psi<R>), dim3(nb), dim3(NT), 0, d->stream,
+                           (const double*)(d->ws + L.off_stage), st, L.pitch, d->p.nx, d->p.ny, wall_bits(d->p));
         HIPCHK(hipGetLastError());
     }
     int rc = upload_job<S>(d, 0, false);

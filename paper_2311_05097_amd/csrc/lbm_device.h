@@ -29,6 +29,7 @@
 // per-tile FP64 partial sums for mass and energy.
 #pragma once
 #include <stdint.h>
+#include <type_traits>
 
 namespace lbm {
 
@@ -56,8 +57,8 @@ struct Coef {
     R k3Ds_16;           // 3 D sigma / 16      (energy)
     R k9s_2D;            // 9 sigma / (2 D)     (energy)
     R kS;                // M (rho1 - rho2) / 2
-    R drho, srho;        // (rho1 - rho2)/2, (rho1 + rho2)/2
-    R dmu, smu;          // (mu1 - mu2)/2, (mu1 + mu2)/2
+    R drho, rho2;        // (rho1 - rho2)/2, rho2: rho = rho2 + (rho1 - rho2)(1 + phi)/2
+    R dmu, mu2;          // (mu1 - mu2)/2, mu2: the same law for the viscosity
     R gx, gy, rho_ref, fbx, fby;
     R solid_eps;
     R ka;                // (c^2 - c_s^2)/2 = (1 - d0)/2
@@ -251,11 +252,13 @@ __device__ __forceinline__ void grad9c(const R* s, int q, int W, R& gx, R& gy) {
 }
 
 // Chemical potential, Eq. (potential), wetting terms through psi.
-template <class R>
-__device__ __forceinline__ R chem_pot(const Coef<R>& c, R ph, R lap, R z, R psi, R lpsi) {
-    const R ph2 = ph * ph;
-    return c.k3s_D * (ph * (ph2 - R(1)) + psi * (R(3) * ph2 + z * z - R(1)))
-         + c.k9s_D * z * z * ph - c.k3Ds_8 * (lap + lpsi);
+// T: the arithmetic of the evaluation (FP64 for the FP32 storage mode, whose
+// order parameter is carried in FP64 in LDS), C: the coefficient set.
+template <class T, class C>
+__device__ __forceinline__ T chem_pot(const C& c, T ph, T lap, T z, T psi, T lpsi) {
+    const T ph2 = ph * ph;
+    return T(c.k3s_D) * (ph * (ph2 - T(1)) + psi * (T(3) * ph2 + z * z - T(1)))
+         + T(c.k9s_D) * z * z * ph - T(c.k3Ds_8) * (lap + lpsi);
 }
 
 // Hermite moments m_k = sum_i h_k(c_i) f_i of the D2Q9 basis
@@ -486,6 +489,13 @@ __global__ __launch_bounds__(TileCfg<TY>::NT) void k_tile(const Job<S>* __restri
                                                          const TileEntry* __restrict__ tiles, int ntiles,
                                                          int t) {
     using R = typename S::R;
+    // the order parameter in LDS: FP64 for FP32 storage, where it is the sum
+    // of the FP32 history value and the small FP32 remainder of the
+    // populations (exact in FP64), so that the stencils of mu (Laplacian) and
+    // grad phi see phi to the precision the populations carry it, not rounded
+    // to FP32 (near phi = +-1 that rounding, 3e-8, put 1e-10 into mu and, divided
+    // by a light phase's density, into the velocity)
+    using RX = typename std::conditional<S::kRel, double, R>::type;
     using A = Access<S>;
     constexpr int NTH = TileCfg<TY>::NT;
     constexpr int NW = NTH / 64;
@@ -497,7 +507,7 @@ __global__ __launch_bounds__(TileCfg<TY>::NT) void k_tile(const Job<S>* __restri
     constexpr int NRING = 6 * W3 + 6 * TY;        // halo ring of the order parameter
     constexpr int NB = (H2 * W2 + NTH - 1) / NTH; // stage-B points per thread
     constexpr int NC = (H1 * W1 + NTH - 1) / NTH; // stage-C points per thread
-    __shared__ R sphi[H3 * W3];
+    __shared__ RX sphi[H3 * W3];
     __shared__ R smu[H2 * W2];
     __shared__ R sz[PART ? H2 * W2 : 1];          // phi0 on the stage-B points (particles)
     __shared__ R sSx[H1 * W1];
@@ -550,18 +560,18 @@ __global__ __launch_bounds__(TileCfg<TY>::NT) void k_tile(const Job<S>* __restri
         const int ly = wv + NW * k;
         const uint32_t o = (uint32_t)(s_row[ly + 3] + s_col[lane + 3]);
         own[k] = o;
-        R* sp = &sphi[(ly + 3) * W3 + lane + 3];
+        RX* sp = &sphi[(ly + 3) * W3 + lane + 3];
         if (MODE == MODE_INIT) {
-            *sp = (R)J.in[o];
+            *sp = (RX)J.in[o];
         } else if (KEEP) {
             const int kk = KEEP ? k : 0;
             A::load_g(cur, pitch, o, c, g[kk], mfix[kk]);
             A::load_f(cur, pitch, o, c, f[kk]);
 #pragma unroll
             for (int v = 0; v < 5; ++v) hp[kk][v] = hprev[v * pitch + o];
-            *sp = S::kRel ? hp[kk][0] + A::phi_of(g[kk], mfix[kk], c) : A::phi_of(g[kk], mfix[kk], c);
+            *sp = S::kRel ? (RX)hp[kk][0] + (RX)A::phi_of(g[kk], mfix[kk], c) : (RX)A::phi_of(g[kk], mfix[kk], c);
         } else {
-            *sp = S::kRel ? hprev[o] + A::phi(cur, pitch, o, c) : A::phi(cur, pitch, o, c);
+            *sp = S::kRel ? (RX)hprev[o] + (RX)A::phi(cur, pitch, o, c) : (RX)A::phi(cur, pitch, o, c);
         }
         zz[k] = st[o];
     }
@@ -579,9 +589,9 @@ __global__ __launch_bounds__(TileCfg<TY>::NT) void k_tile(const Job<S>* __restri
         }
         const uint32_t o = (uint32_t)(s_row[ly] + s_col[lx]);
         if (MODE == MODE_INIT)
-            sphi[ly * W3 + lx] = (R)J.in[o];
+            sphi[ly * W3 + lx] = (RX)J.in[o];
         else if (S::kRel)
-            sphi[ly * W3 + lx] = hprev[o] + A::phi(cur, pitch, o, c);
+            sphi[ly * W3 + lx] = (RX)hprev[o] + (RX)A::phi(cur, pitch, o, c);
         else
             sphi[ly * W3 + lx] = A::phi(cur, pitch, o, c);
     }
@@ -625,7 +635,7 @@ __global__ __launch_bounds__(TileCfg<TY>::NT) void k_tile(const Job<S>* __restri
         if (p < H2 * W2) {
             const int ly = p / W2, lx = p - ly * W2;
             const int q = (ly + 1) * W3 + (lx + 1);
-            smu[p] = chem_pot(c, sphi[q], lap9(sphi, q, W3), bz[k], bpsi[k], blp[k]);
+            smu[p] = (R)chem_pot<RX>(c, sphi[q], lap9(sphi, q, W3), (RX)bz[k], (RX)bpsi[k], (RX)blp[k]);
             if (PART) sz[p] = bz[k];
         }
     }
@@ -694,15 +704,26 @@ __global__ __launch_bounds__(TileCfg<TY>::NT) void k_tile(const Job<S>* __restri
         const int q3 = (ly + 3) * W3 + (lane + 3);
         const int q2 = (ly + 2) * W2 + (lane + 2);
         const int q1 = (ly + 1) * W1 + (lane + 1);
-        const R ph = sphi[q3];
+        const RX phx = sphi[q3];
+        const R ph = (R)phx;
         R dpx, dpy;
-        grad9(sphi, q3, W3, dpx, dpy);
+        {
+            RX gx, gy;
+            grad9(sphi, q3, W3, gx, gy);
+            dpx = (R)gx;
+            dpy = (R)gy;
+        }
         const R mu = smu[q2];
         const R Sx = sSx[q1], Sy = sSy[q1];
         const R z = zz[k];
-        // density and viscosity laws (Eq. rho) on phi clamped to [-1, 1]
-        const R rho = c.srho + c.drho * clamp1(ph);
-        const R muv = c.smu + c.dmu * clamp1(ph);
+        // density and viscosity laws (Eq. rho) on phi clamped to [-1, 1],
+        // written as rho2 + (rho1 - rho2)(1 + phi)/2: the light phase's density
+        // is then not the difference of two O(1) numbers (at density ratio
+        // 1000 that difference lost 4 of FP32's 7 digits, and the velocity
+        // j / rho with them); 1 + phi comes from the FP64 phi of FP32 storage
+        const R op = (R)(RX(1) + clamp1(phx));
+        const R rho = c.rho2 + c.drho * op;
+        const R muv = c.mu2 + c.dmu * op;
         // neighbours for the push (periodic); bb: the walls next to this node
         // (bit 0 below, 1 above, 2 left, 3 right), whose crossing populations
         // are reflected at the store, and across which neighbours mirror
@@ -721,7 +742,9 @@ __global__ __launch_bounds__(TileCfg<TY>::NT) void k_tile(const Job<S>* __restri
             const R emu = c.eta * mu, ia = R(1) / c.a;
             const R jxa = ph * ux * ia, jya = ph * uy * ia;
             R m[9], gg[9], ff[9];
-            gg[0] = S::kRel ? (c.w0 - R(1)) * emu : ph + (c.w0 - R(1)) * emu;
+            // relative rest population: g_0^eq - phi_h with phi_h = FP32(phi),
+            // the history value below; phi - phi_h keeps phi's lower bits
+            gg[0] = S::kRel ? (c.w0 - R(1)) * emu + (R)(phx - (RX)ph) : ph + (c.w0 - R(1)) * emu;
             gg[1] = c.w1 * (emu + jxa);
             gg[3] = c.w1 * (emu - jxa);
             gg[2] = c.w1 * (emu + jya);
@@ -750,7 +773,12 @@ __global__ __launch_bounds__(TileCfg<TY>::NT) void k_tile(const Job<S>* __restri
         R wx, wy;
         grad9(sw, q1, W1, wx, wy);
         R dcx, dcy;
-        grad9c(sphi, q3, W3, dcx, dcy);
+        {
+            RX gx, gy;
+            grad9c(sphi, q3, W3, gx, gy);
+            dcx = (R)gx;
+            dcy = (R)gy;
+        }
         const R drx = c.drho * dcx, dry = c.drho * dcy;
         // free particles (Sec. 2.4): the owning particle's solid velocity
         // u_s = u_p + omega_p x (x - x_p) and the force mu_phi0 grad phi0 of
@@ -772,7 +800,7 @@ __global__ __launch_bounds__(TileCfg<TY>::NT) void k_tile(const Job<S>* __restri
                 R gzx, gzy;
                 grad9(sz, q2, W2, gzx, gzy);
                 const R muz = c.k9s_D * z * ph * ph + c.k3s_D * cth * ph * (R(3) * z * z + ph * ph - R(1))
-                            - c.k3Ds_8 * cth * lap9(sphi, q3, W3);
+                            - c.k3Ds_8 * cth * (R)lap9(sphi, q3, W3);
                 Fpx = muz * gzx;
                 Fpy = muz * gzy;
             }
@@ -812,7 +840,7 @@ __global__ __launch_bounds__(TileCfg<TY>::NT) void k_tile(const Job<S>* __restri
         const R s2a = sdiv<S>(R(1), tau_a), s2b = sdiv<S>(R(1), tau_b);
         const R udr = ux * drx + uy * dry;
         const R q = rho * (ux * ux + uy * uy) - (Sx * ux + Sy * uy);
-        const R rhop = c.srho + c.drho * clamp1(php);
+        const R rhop = c.rho2 + c.drho * (R(1) + clamp1(php));
         const R qp = rhop * (uxp * uxp + uyp * uyp) - (Sxp * uxp + Syp * uyp);
         R P = R(0);
         if (!first) {
@@ -824,7 +852,7 @@ __global__ __launch_bounds__(TileCfg<TY>::NT) void k_tile(const Job<S>* __restri
 
         if (MODE == MODE_OUT) {
             if (J.out) {
-                J.out[o] = (double)ph;
+                J.out[o] = (double)phx;
                 J.out[pitch + o] = (double)ux;
                 J.out[2 * pitch + o] = (double)uy;
                 J.out[3 * pitch + o] = (double)P;
@@ -996,20 +1024,31 @@ __global__ __launch_bounds__(NT) void k_part_base(const double* __restrict__ in,
     base[pitch + o] = (R)in[2 * pitch + o];
 }
 
-// Laplacian of psi (static wetting field), periodic, or mirrored at walls.
+// Laplacian of psi (static wetting field), periodic, or mirrored at walls,
+// evaluated in FP64 on psi = cos(theta) clamp(phi0) from the FP64 input planes
+// (staging planes 1 and 2) and rounded once: a Laplacian of psi values already
+// rounded to the storage type would carry their rounding (about 1e-7 in FP32)
+// into the chemical potential next to every solid.
+__device__ __forceinline__ double psi_in(const double* in, int64_t pitch, int64_t o) {
+    double z = in[pitch + o];
+    z = z < 0.0 ? 0.0 : (z > 1.0 ? 1.0 : z);
+    return in[2 * pitch + o] * z;
+}
 template <class R>
-__global__ __launch_bounds__(NT) void k_lap_psi(R* __restrict__ st, int64_t pitch, int nx, int ny, int walls) {
+__global__ __launch_bounds__(NT) void k_lap_psi(const double* __restrict__ in, R* __restrict__ st, int64_t pitch,
+                                                int nx, int ny, int walls) {
     const int64_t o = (int64_t)blockIdx.x * NT + threadIdx.x;
     if (o >= (int64_t)nx * ny) return;
     const int y = (int)(o / nx), x = (int)(o - (int64_t)y * nx);
-    const R* psi = st + pitch;
     const int xe = imgof(x + 1, nx, walls & 2), xw = imgof(x - 1, nx, walls & 2);
     const int64_t rc = (int64_t)y * nx, rn = (int64_t)imgof(y + 1, ny, walls & 1) * nx;
     const int64_t rs = (int64_t)imgof(y - 1, ny, walls & 1) * nx;
-    const R c4 = R(4) * psi[o];
-    const R ax = (psi[rc + xe] + psi[rc + xw]) + (psi[rn + x] + psi[rs + x]);
-    const R dg = (psi[rn + xe] + psi[rn + xw]) + (psi[rs + xe] + psi[rs + xw]);
-    st[2 * pitch + o] = (ax - c4) * R(2.0 / 3.0) + (dg - c4) * R(1.0 / 6.0);
+    const double c4 = 4.0 * psi_in(in, pitch, o);
+    const double ax = (psi_in(in, pitch, rc + xe) + psi_in(in, pitch, rc + xw)) +
+                      (psi_in(in, pitch, rn + x) + psi_in(in, pitch, rs + x));
+    const double dg = (psi_in(in, pitch, rn + xe) + psi_in(in, pitch, rn + xw)) +
+                      (psi_in(in, pitch, rs + xe) + psi_in(in, pitch, rs + xw));
+    st[2 * pitch + o] = (R)((ax - c4) * (2.0 / 3.0) + (dg - c4) * (1.0 / 6.0));
 }
 
 // ---------------------------------------------------------- free particles

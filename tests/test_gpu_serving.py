@@ -41,3 +41,37 @@ def test_served_jobs_equal_solo_runs(gpu, storage):
         assert a[j.job_id].mass_drift == b[j.job_id].mass_drift
         print(f"\njob {j.job_id} {j.side}^2: identical, drift {a[j.job_id].mass_drift:.1e}")
     assert batched.ticks > 1
+
+
+@pytest.fixture(scope="module")
+def served_vs_oracle_jobs():
+    """Two small jobs of the drop-on-slab stream (128^2 at 40 and 140 degrees,
+    density ratios 30 and 200) and the oracle's phi after their step budgets."""
+    from oracle.oracle import Oracle
+    jobs = [W.JobSpec(0, 128, 40.0, 30.0, 600, 0.0), W.JobSpec(1, 128, 140.0, 200.0, 400, 0.0)]
+    ref = {}
+    for j in jobs:
+        w = j.workload()
+        o = Oracle(w.params, *w.arrays())
+        o.step(j.steps)
+        ref[j.job_id] = o.field("phi")
+    return jobs, ref
+
+
+@pytest.mark.parametrize("storage,tol", [("fp32", 1e-5), ("fp16dev", 1e-3), ("bf16dev", 1e-3)])
+def test_served_job_matches_oracle(gpu, served_vs_oracle_jobs, storage, tol):
+    """A job served in a batch, compared with the FP64 oracle itself (not only
+    with its solo run): the relative phi error in the 2-norm and the max-norm
+    within the storage mode's bar (1e-5 for FP32, 1e-3 for the 16-bit
+    deviation modes)."""
+    from paper_2311_05097_amd import serve
+    from parity import rel, relmax
+    jobs, ref = served_vs_oracle_jobs
+    srv = serve.Server(storage=storage, budget_bytes=1 << 30, tick_steps=100, tile=8, keep_phi=True)
+    res = srv.run(jobs, realtime=False)
+    srv.close()
+    for j in res.jobs:
+        assert j.status == "done", j
+        e2, em = rel(j.phi, ref[j.job_id]), relmax(j.phi, ref[j.job_id])
+        print(f"\nserved job {j.job_id} {storage}: phi error {e2:.2e} / {em:.2e}, mass drift {j.mass_drift:.1e}")
+        assert e2 <= tol and em <= tol
