@@ -186,6 +186,19 @@ size_t lbm_smooth_workspace_bytes(int32_t nx, int32_t ny);
 int lbm_smooth_solid(const lbm_params *p, int32_t iters, double dtau, void *dev_workspace, size_t bytes,
                      void *hip_stream, const double *solid, double *phi0);
 
+/* For callers that cannot allocate device memory (code under stream capture,
+ * tight serving loops, hosts that forbid allocation): lbm_smooth_solid without
+ * a workspace.  Its three FP64 planes live in a device array of the library
+ * (3 * LBM_NOALLOC_MAX_NODES doubles, 6 MiB), one per device, held until the
+ * process ends; the call makes no device allocation.  Same arguments, result
+ * and errors as lbm_smooth_solid, plus LBM_EINVAL for grids of more than
+ * LBM_NOALLOC_MAX_NODES nodes.  Every call on a device uses that device's one
+ * array: calls that overlap on one device (other host threads, other streams)
+ * race and must be serialised by the caller.  Blocks. */
+#define LBM_NOALLOC_MAX_NODES (1 << 18)
+int lbm_smooth_solid_noalloc(const lbm_params *p, int32_t iters, double dtau, void *hip_stream,
+                             const double *solid, double *phi0);
+
 /* Procedure steps 2-6, nsteps >= 0 times: one fused kernel per step (stencils
  * for mu, grad phi, S and F_c from a halo tile, velocity and pressure
  * recovery, both MRT collisions, streaming).  Enqueued on the stream; returns

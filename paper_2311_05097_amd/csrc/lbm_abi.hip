@@ -14,6 +14,7 @@
 #include <cmath>
 #include <algorithm>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -627,25 +628,27 @@ size_t lbm_smooth_workspace_bytes(int32_t nx, int32_t ny) {
     return 3 * up((size_t)nx * ny * 8);
 }
 
-int lbm_smooth_solid(const lbm_params* p, int32_t iters, double dtau, void* dev_workspace, size_t bytes,
-                     void* hip_stream, const double* solid, double* phi0) {
+namespace {
+// The arguments of a smoothing call, checked; dtau resolved.
+int smooth_args(const lbm_params* p, int32_t iters, double& dtau, const double* solid, const double* phi0) {
     int rc = validate(p);
     if (rc) return rc;
-    if (!solid || !phi0 || !dev_workspace) return fail(LBM_EINVAL, "NULL argument");
+    if (!solid || !phi0) return fail(LBM_EINVAL, "NULL argument");
     if (iters < 0 || iters > (1 << 20)) return fail(LBM_EINVAL, "iters out of range");
     if (!std::isfinite(dtau)) return fail(LBM_EINVAL, "dtau must be finite");
-    if ((uintptr_t)dev_workspace % ALIGN) return fail(LBM_EINVAL, "workspace must be 256-byte aligned");
-    const size_t need = lbm_smooth_workspace_bytes(p->nx, p->ny);
-    if (bytes < need) return fail(LBM_ENOMEM, "workspace too small");
-    const int64_t N = (int64_t)p->nx * p->ny;
     const double kappa = p->D * p->D / 8.0, L = 16.0 / 3.0;
     // default: half the stability limit of the step linearised about chi = +-1
     if (dtau <= 0.0) dtau = 0.5 / (kappa * L * L + 2.0 * L);
-    hipStream_t st = (hipStream_t)hip_stream;
-    char* ws = (char*)dev_workspace;
-    double* chi = (double*)ws;
-    double* mu = (double*)(ws + up((size_t)N * 8));
-    double* nxt = (double*)(ws + 2 * up((size_t)N * 8));
+    return LBM_OK;
+}
+
+// The smoothing itself on three FP64 device planes of N nodes each: the host
+// solid is copied into the third, `iters` explicit steps alternate the first
+// and third, and phi0 is copied back.  Blocks on the stream.
+int smooth_run(const lbm_params* p, int32_t iters, double dtau, hipStream_t st, double* chi, double* mu,
+               double* nxt, const double* solid, double* phi0) {
+    const int64_t N = (int64_t)p->nx * p->ny;
+    const double kappa = p->D * p->D / 8.0;
     const unsigned nb = (unsigned)((N + NT - 1) / NT);
     const int w = wall_bits(*p);
     HIPCHK(hipMemcpyAsync(nxt, solid, (size_t)N * 8, hipMemcpyHostToDevice, st));
@@ -660,6 +663,62 @@ int lbm_smooth_solid(const lbm_params* p, int32_t iters, double dtau, void* dev_
     HIPCHK(hipMemcpyAsync(phi0, nxt, (size_t)N * 8, hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
     return LBM_OK;
+}
+
+// Scratch of the allocation-free smoothing: three FP64 planes of at most
+// LBM_NOALLOC_MAX_NODES nodes, one copy per device for the life of the
+// process.  In host code `scratch` is only a stand-in for the symbol: its
+// device address, per device, comes from hipGetSymbolAddress at the first
+// call on that device and is the only form in which it is passed on.
+__device__ __align__(256) double scratch[3 * (size_t)LBM_NOALLOC_MAX_NODES];
+constexpr int MAX_DEVICES = 64;
+std::mutex scratch_mu;
+double* scratch_ptr[MAX_DEVICES] = {};
+
+int scratch_for_current_device(double** out) {
+    int dev = -1;
+    HIPCHK(hipGetDevice(&dev));
+    if (dev < 0 || dev >= MAX_DEVICES) return fail(LBM_EDEVICE, "device index out of range");
+    std::lock_guard<std::mutex> lock(scratch_mu);
+    if (!scratch_ptr[dev]) {
+        void* ptr = nullptr;
+        HIPCHK(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+        if (!ptr) return fail(LBM_EDEVICE, "no device address for the scratch array");
+        scratch_ptr[dev] = (double*)ptr;
+    }
+    *out = scratch_ptr[dev];
+    return LBM_OK;
+}
+}  // namespace
+
+int lbm_smooth_solid(const lbm_params* p, int32_t iters, double dtau, void* dev_workspace, size_t bytes,
+                     void* hip_stream, const double* solid, double* phi0) {
+    int rc = smooth_args(p, iters, dtau, solid, phi0);
+    if (rc) return rc;
+    if (!dev_workspace) return fail(LBM_EINVAL, "NULL argument");
+    if ((uintptr_t)dev_workspace % ALIGN) return fail(LBM_EINVAL, "workspace must be 256-byte aligned");
+    const size_t need = lbm_smooth_workspace_bytes(p->nx, p->ny);
+    if (bytes < need) return fail(LBM_ENOMEM, "workspace too small");
+    const size_t plane = up((size_t)p->nx * p->ny * 8);
+    char* ws = (char*)dev_workspace;
+    return smooth_run(p, iters, dtau, (hipStream_t)hip_stream, (double*)ws, (double*)(ws + plane),
+                      (double*)(ws + 2 * plane), solid, phi0);
+}
+
+int lbm_smooth_solid_noalloc(const lbm_params* p, int32_t iters, double dtau, void* hip_stream,
+                             const double* solid, double* phi0) {
+    int rc = smooth_args(p, iters, dtau, solid, phi0);
+    if (rc) return rc;
+    const int64_t N = (int64_t)p->nx * p->ny;
+    if (N > (int64_t)LBM_NOALLOC_MAX_NODES)
+        return fail(LBM_EINVAL, "grid of " + std::to_string(N) + " nodes exceeds the " +
+                                    std::to_string((long long)LBM_NOALLOC_MAX_NODES) +
+                                    "-node limit of the allocation-free smoothing");
+    double* base = nullptr;
+    if ((rc = scratch_for_current_device(&base))) return rc;
+    const size_t plane = (size_t)LBM_NOALLOC_MAX_NODES;
+    return smooth_run(p, iters, dtau, (hipStream_t)hip_stream, base, base + plane, base + 2 * plane, solid,
+                      phi0);
 }
 
 int lbm_particles(lbm_domain* d, double* state, double* outputs) {

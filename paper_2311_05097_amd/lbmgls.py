@@ -27,7 +27,9 @@ EXPORTED = [
     "lbm_batch_workspace_bytes", "lbm_batch_create", "lbm_batch_add", "lbm_batch_remove",
     "lbm_batch_step", "lbm_batch_size", "lbm_batch_destroy", "lbm_last_error",
     "lbm_create_particles", "lbm_particles", "lbm_smooth_workspace_bytes", "lbm_smooth_solid",
+    "lbm_smooth_solid_noalloc",
 ]
+NOALLOC_MAX_NODES = 1 << 18  # LBM_NOALLOC_MAX_NODES of include/lbmgls.h
 
 
 class LbmError(RuntimeError):
@@ -106,6 +108,7 @@ def lib():
             "lbm_smooth_workspace_bytes": (ctypes.c_size_t, [ctypes.c_int32, ctypes.c_int32]),
             "lbm_smooth_solid": (ctypes.c_int, [P, ctypes.c_int32, ctypes.c_double, _VP, ctypes.c_size_t, _VP,
                                                 _D, _D]),
+            "lbm_smooth_solid_noalloc": (ctypes.c_int, [P, ctypes.c_int32, ctypes.c_double, _VP, _D, _D]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(L, name)
@@ -298,6 +301,18 @@ def smooth_solid(params: dict, solid, iters: int = 20, dtau: float = 0.0):
     _check(lib().lbm_smooth_solid(ctypes.byref(lp), int(iters), float(dtau), _VP(ptr), nbytes,
                                   current_stream_handle(), sp, out.ctypes.data_as(_D)))
     del buf
+    return out
+
+
+def smooth_solid_noalloc(params: dict, solid, iters: int = 20, dtau: float = 0.0):
+    """As smooth_solid, through the allocation-free entry point
+    (lbm_smooth_solid_noalloc): no workspace, grids of at most
+    NOALLOC_MAX_NODES nodes."""
+    solid, sp = _arr(solid, (params["ny"], params["nx"]))
+    out = np.zeros_like(solid)
+    lp = make_params(params)
+    _check(lib().lbm_smooth_solid_noalloc(ctypes.byref(lp), int(iters), float(dtau), current_stream_handle(), sp,
+                                          out.ctypes.data_as(_D)))
     return out
 
 
