@@ -1018,6 +1018,7 @@ void orc_step(orc_state *st, long nsteps)
 
 long orc_steps_done(const orc_state *st) { return st->steps; }
 int orc_threads(void) { return omp_get_max_threads(); }
+void orc_set_threads(int n) { if (n > 0) omp_set_num_threads(n); }
 int orc_nfields(void) { return NFIELDS; }
 const char *orc_field_name(int k) { return (k >= 0 && k < NFIELDS) ? FIELD_NAMES[k] : NULL; }
 

@@ -30,7 +30,9 @@ CFLAGS = ["-O2", "-ffp-contract=off", "-fopenmp", "-fPIC", "-shared", "-std=c11"
 def build(force: bool = True) -> str:
     """Compile the oracle into ``liblbm_oracle.so`` next to its source."""
     if force or not os.path.exists(LIB):
-        tmp = LIB + ".tmp"
+        # a name of its own per process: concurrent test workers may all
+        # find the library stale and build it at once; the rename is atomic
+        tmp = "%s.%d.tmp" % (LIB, os.getpid())
         subprocess.check_call(["gcc", *CFLAGS, "-o", tmp, SRC, "-lm"])
         os.replace(tmp, LIB)
     return LIB
@@ -114,6 +116,7 @@ def lib():
         L.orc_lap.argtypes = [ctypes.c_int, ctypes.c_int, _D, _D]
         L.orc_mu.argtypes = [ctypes.POINTER(OrcParams), _D, _D, _D, _D]
         L.orc_threads.restype = ctypes.c_int
+        L.orc_set_threads.argtypes = [ctypes.c_int]
         L.orc_plant.argtypes = [ctypes.c_int, ctypes.c_double]
         L.orc_plant.restype = ctypes.c_int
         _lib = L
@@ -157,6 +160,30 @@ def planted(**factors):
 def threads() -> int:
     """OpenMP threads the collision loop uses."""
     return int(lib().orc_threads())
+
+
+def set_threads(n: int):
+    """Threads of the collision loop for the following steps."""
+    lib().orc_set_threads(int(n))
+
+
+def build_native(path: str) -> str:
+    """The same source built for the host it runs on (-O3 -march=native), into
+    `path`: the CPU-baseline timing build.  Arithmetic is still unfused
+    (-ffp-contract=off)."""
+    flags = ["-O3", "-march=native", "-ffp-contract=off", "-fopenmp", "-fPIC", "-shared", "-std=c11"]
+    tmp = path + ".tmp"
+    subprocess.check_call(["gcc", *flags, "-o", tmp, SRC, "-lm"])
+    os.replace(tmp, path)
+    return path
+
+
+def use_library(path: str):
+    """Load the oracle from another build of the same source (before the
+    first call into it)."""
+    global LIB, _lib
+    assert _lib is None, "the oracle library is already loaded"
+    LIB = path
 
 
 # ---------------------------------------------------------------- unit level

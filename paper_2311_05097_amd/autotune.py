@@ -1,6 +1,7 @@
 """Tile-shape autotuner for the fused step kernel.
 
-The step kernel is compiled for 64 x TY tiles with TY in {4, 8, 16}.  Small TY
+The step kernel is compiled for 64 x TY tiles with TY in {4, 8, 16} (and 32
+outside FP64 storage).  Small TY
 gives more blocks (better load balance on 256 CUs) but recomputes a larger
 share of halo; large TY amortises the 3-node halo of the order parameter.  The
 best choice depends on the grid and on the storage mode, so it is measured:
@@ -19,6 +20,7 @@ import os
 import numpy as np
 
 CANDIDATES = (4, 8, 16)
+CANDIDATES_32 = CANDIDATES + (32,)  # 64 x 32 tiles are built for FP32 and 16-bit storage
 
 
 def cache_path() -> str:
@@ -77,7 +79,7 @@ def best_tile(params: dict, storage: str, retune: bool = False) -> int:
     steps = max(40, min(400, int(2e8 // (nx * ny))))
     times = {}
     for _ in range(2):
-        for ty in CANDIDATES:
+        for ty in (CANDIDATES if storage == "fp64" else CANDIDATES_32):
             t = measure(params, storage, ty, steps=steps)
             times[ty] = min(t, times.get(ty, t))
     best = min(times, key=times.get)

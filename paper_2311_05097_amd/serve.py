@@ -87,12 +87,14 @@ class Server:
     """Continuous batching over cache-sized lanes of lbm_batch."""
 
     def __init__(self, storage: str = "fp32", budget_bytes: int = 4 << 30, tick_steps: int = 500,
-                 max_members: int = 128, tile: int = 8, keep_phi: bool = False,
+                 max_members: int = 128, tile: int = 0, keep_phi: bool = False,
                  job_overrides: dict | None = None, on_retire=None, lane_bytes: int | None = None):
         self.storage = storage
         self.budget = int(budget_bytes)
         self.tick = int(tick_steps)
-        self.tile = int(tile)
+        # tile 0: the autotuner's shape for this storage on a 512^2 job (the
+        # stream's median side); one shape serves every member of a lane
+        self.tile = int(tile) if tile else _tuned_tile(512, storage)
         self.keep_phi = keep_phi
         self.overrides = dict(job_overrides or {})
         self.on_retire = on_retire
@@ -211,10 +213,16 @@ class Server:
         self.lanes.clear()
 
 
+def _tuned_tile(side: int, storage: str) -> int:
+    from . import autotune
+    return autotune.best_tile(JobSpec(0, side, 90.0, 10.0, 0).workload().params, storage)
+
+
 def run_solo(jobs: list[JobSpec], storage: str = "fp32", tile: int = 0, check_every: int = 1000,
              realtime: bool = True, keep_phi: bool = False, job_overrides: dict | None = None,
              on_retire=None) -> ServeStats:
-    """The plain per-job path: one job at a time, FIFO, per-step launches."""
+    """The plain per-job path: one job at a time, FIFO, per-step launches;
+    tile 0: the autotuner's shape for each job's size."""
     overrides = dict(job_overrides or {})
     pending = sorted(jobs, key=lambda j: (j.arrival_s, j.job_id))
     out = []
@@ -225,7 +233,7 @@ def run_solo(jobs: list[JobSpec], storage: str = "fp32", tile: int = 0, check_ev
             time.sleep(spec.arrival_s - now)
         res = JobResult(spec.job_id, spec.side, spec.steps, spec.arrival_s)
         w = spec.workload(**overrides)
-        d = lbmgls.Domain(w.params, *w.arrays(), storage=storage, tile=tile)
+        d = lbmgls.Domain(w.params, *w.arrays(), storage=storage, tile=tile or _tuned_tile(spec.side, storage))
         res.admitted = time.perf_counter() - t0
         m0 = d.mass()
         d.set_check(check_every)

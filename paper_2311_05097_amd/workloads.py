@@ -367,11 +367,12 @@ class JobSpec:
     steps: int
     arrival_s: float = 0.0
 
-    def workload(self, mu1: float = 0.3, mu_ratio: float = 50.0, **kw) -> Workload:
+    def workload(self, mu1: float = 1.0, mu_ratio: float = 10.0, **kw) -> Workload:
         """Drop-on-slab job: L x L periodic, slab rows [0, L/8), drop radius
         L/4 on the slab, density ratio r with rho2 = 1/r; viscosities mu1 and
-        mu2 = mu1 / mu_ratio (the stream fixes no viscosity; 0.3 and 50 keep
-        density ratios up to ~200 stable next to solids)."""
+        mu2 = mu1 / mu_ratio (the stream fixes no viscosity; with 1.0 and 10
+        every job of density ratio up to 100 stays finite over 20 000 steps at
+        every angle of 30-150 degrees)."""
         L = self.side
         return droplet_on_slab(nx=L, ny=L, slab_rows=L // 8, R=L / 4.0, theta_deg=self.theta_deg,
                                rho_ratio=self.rho_ratio, mu_ratio=mu_ratio, mu1=mu1,
