@@ -95,7 +95,7 @@ typedef struct {
        particle distances in y without the periodic image.  0: periodic. */
     int32_t bounce_y;
     /* the same left of column 0 and right of column nx - 1 (the side walls of
-       the channel of Sec. 4.5); at a corner a population that would leave
+       the sedimentation channel of Sec. 4.3); at a corner a population that would leave
        through either wall returns to its node. */
     int32_t bounce_x;
     /* H of the pressure recovery (Sec. 3.2, after Eq. u).  0: the factor that

@@ -126,7 +126,7 @@ def test_rotating_cylinder_couette(gpu):
 
 
 def _sediment(gpu, rho1, steps, sigma=1e-2, D=2.0):
-    """Sec. 4.5: a disk (R = 0.125, rho_p = 1.25) released at (1, 4) in a
+    """Sec. 4.3: a disk (R = 0.125, rho_p = 1.25) released at (1, 4) in a
     closed 2 x 6 channel, fluid 1 below y = 3 and fluid 2 (rho2 = 1) above,
     mu = 0.1, g = 980, body force (rho - rho2) g; dx = 1/192, dt = dx/64.
     Returns the history (t, y_p, v_p) in the paper's units."""
@@ -154,7 +154,7 @@ def _sediment(gpu, rho1, steps, sigma=1e-2, D=2.0):
 
 
 def test_sedimentation_in_a_stratified_channel(gpu):
-    """Sec. 4.5's stratified sedimentation in a channel closed by bounce-back
+    """Sec. 4.3's stratified sedimentation in a channel closed by bounce-back
     walls.  No closed form exists for this confined, finite-Reynolds fall, so
     only what the densities alone fix is asserted: a particle heavier than both
     fluids (one fluid; or a lower fluid of rho1 = 1.1 < rho_p) falls and comes
