@@ -42,21 +42,29 @@
  *            powers coincide; the last row is the one orthogonal to the
  *            lower ones under the weights).  M_0 holds the raw monomials,
  *            N_H the lower-triangular map to these rows, C_d = I (c = 1).
- *            S_H^1 = diag(s0, s_1phi x3, s2 x6, s3 x4, s4),
- *            S_H^2 = diag(s0, s1 x3, s_2a x3, s_2b x3, s3 x4, s4).
+ *            Phase field: S_H^1 = diag(s0, s_1phi x3, s2 x6, s3 x4, s4); flow:
+ *            S_H^2 of R3-RATES.
  *   R3-FD    gradient and Laplacian use the isotropic D3Q15 weights at
  *            c_s^2 = 1/3 (2/9, 1/9, 1/72).
  *   R3-NU    the viscosity relations of Sec. 3.2 as printed:
  *            nu = (1/s_2a - 1/2)(c^2 - c_s^2)/2 = (1/s_2b - 1/2) c_s^2 (on this
  *            lattice the diagonal and off-diagonal second moments carry the
  *            same third-moment fluxes as on D2Q9).
- *   R3-H     H = -2 K (1 - 3 d0)(1/s_2a - 1/2), the factor that cancels the
- *            first-order non-equilibrium part of sum_{i != 0} f_i on this
- *            lattice: the zeroth moment carries -u.grad(rho)/2 and the trace
- *            of the second Hermite moments
- *            [2 (1 - 3 d0)/s_2a - (3 - 7 d0)/2] u.grad(rho) - d_t(q)/2.  The
- *            printed 3-D factor K [(1 - d0)/s_0 - (3 - 7 d0)/s_2a + (1 - 3 d0)]
- *            equals it when s_0 = s_2a; h_form = 1 selects it.
+ *   R3-RATES the flow distributions relax their zeroth moment and their
+ *            fourth-order moment with the per-node s_2a, like the trace of the
+ *            second moments: S_H^2 = diag(s_2a, s1 x3, s_2a x3, s_2b x3, s3 x4,
+ *            s_2a).  These three scalar moments make up the rest population;
+ *            relaxed at different rates (s_0 = s_4 = 1 as in two dimensions)
+ *            the linearised scheme has a growing mode at the wave vector
+ *            (pi, pi, pi) for every s_2a > 1 (a growth factor up to 1.3 per
+ *            step), relaxed at one rate it has none for any s_2a in (0, 2).
+ *   R3-H     H = K [(1 - d0)/s_0 - (3 - 7 d0)/s_2a + (1 - 3 d0)] as printed,
+ *            which with s_0 = s_2a (R3-RATES) is -2 K (1 - 3 d0)(1/s_2a - 1/2):
+ *            the factor that cancels the first-order non-equilibrium part of
+ *            sum_{i != 0} f_i on this lattice (the zeroth moment carries
+ *            -u.grad(rho)/2, the trace of the second Hermite moments
+ *            [2 (1 - 3 d0)/s_2a - (3 - 7 d0)/2] u.grad(rho) - d_t(q)/2).  So
+ *            the printed factor and the derived one agree here.
  *   and, as in two dimensions: the Cahn-Hilliard phase equation; F_c from the
  *   current S and the lagged velocity; backward differences for d/dt with
  *   d_t(rho u u) = u F + F u; (1 - phi0) floored at solid_eps in the
@@ -77,12 +85,13 @@
 /* ---- parameters (layout mirrored by the ctypes wrapper in oracle3d.py) ---- */
 typedef struct {
     int32_t nx, ny, nz;
-    int32_t h_form;              /* R3-H: 0 derived, 1 as printed           */
+    int32_t pad;                 /* unused (keeps the doubles aligned)      */
     double d0;                   /* c_s^2 / c^2                             */
     double sigma, D, M;          /* Eq. (2energyDensity), mobility          */
     double rho1, rho2, mu1, mu2; /* Eq. (rho) and the viscosity law         */
     double tau_phi;              /* 1 / s_1phi                              */
-    double s0, s1, s2, s3, s4;   /* the remaining relaxation rates          */
+    double s0, s1, s2, s3, s4;   /* the remaining relaxation rates (s0, s2,
+                                    s4: phase field only, R3-RATES)         */
     double gx, gy, gz, rho_ref;  /* gravity part of F_b                     */
     double fbx, fby, fbz;        /* driving part of F_b                     */
     double solid_eps;            /* floor of 1 - phi0 in the viscosity      */
@@ -394,10 +403,8 @@ static void viscous_rates(const orc3_params *p, double rho, double muv, double p
     const double tau_b = nu / cs2 + 0.5;
     *s2a = 1.0 / tau_a;
     *s2b = 1.0 / tau_b;
-    if (p->h_form == 1)
-        *H = K * ((1.0 - d0) / p->s0 - (3.0 - 7.0 * d0) * tau_a + (1.0 - 3.0 * d0));
-    else
-        *H = -2.0 * K * (1.0 - 3.0 * d0) * (tau_a - 0.5);
+    /* the printed factor with s_0 = s_2a (R3-RATES) */
+    *H = K * ((1.0 - d0) * tau_a - (3.0 - 7.0 * d0) * tau_a + (1.0 - 3.0 * d0));
 }
 
 /* Eqs. (uStar) and (u) at one node.  out = u* (3), f dt (3), u (3), s2a,
@@ -591,8 +598,9 @@ static void collide_all(orc3_state *st)
         }
         const double rf[3] = {rho * F[F_AX][o], rho * F[F_AY][o], rho * F[F_AZ][o]};
         orc3_fsrc(d0, u, dr, Fv, rf, M2, F2);
-        const double sf[Q] = {p->s0, p->s1, p->s1, p->s1, F[F_S2A][o], F[F_S2A][o], F[F_S2A][o],
-                              F[F_S2B][o], F[F_S2B][o], F[F_S2B][o], p->s3, p->s3, p->s3, p->s3, p->s4};
+        const double s2a = F[F_S2A][o], s2b = F[F_S2B][o];
+        const double sf[Q] = {s2a, p->s1, p->s1, p->s1, s2a, s2a, s2a, s2b, s2b, s2b,
+                              p->s3, p->s3, p->s3, p->s3, s2a}; /* R3-RATES */
         lam_from(st->MH, st->MHinv, sf, Lam);
         collide(Lam, fi, fe, F2, out);
         for (int i = 0; i < Q; ++i) st->fpost[i * N + o] = out[i];

@@ -32,7 +32,7 @@ def build(force: bool = True) -> str:
 
 class Orc3Params(ctypes.Structure):
     _fields_ = [
-        ("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32), ("h_form", ctypes.c_int32),
+        ("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32), ("pad", ctypes.c_int32),
         ("d0", ctypes.c_double), ("sigma", ctypes.c_double), ("D", ctypes.c_double), ("M", ctypes.c_double),
         ("rho1", ctypes.c_double), ("rho2", ctypes.c_double), ("mu1", ctypes.c_double), ("mu2", ctypes.c_double),
         ("tau_phi", ctypes.c_double),
@@ -44,7 +44,7 @@ class Orc3Params(ctypes.Structure):
     ]
 
 
-OPTIONAL = {"h_form": 0, "gx": 0.0, "gy": 0.0, "gz": 0.0, "rho_ref": 0.0, "fbx": 0.0, "fby": 0.0, "fbz": 0.0}
+OPTIONAL = {"pad": 0, "gx": 0.0, "gy": 0.0, "gz": 0.0, "rho_ref": 0.0, "fbx": 0.0, "fby": 0.0, "fbz": 0.0}
 PLANT_TERMS = {"H": 0, "KDT": 1, "G": 2, "FC": 3, "ISO": 4, "UDR": 5}
 
 _lib = None
