@@ -217,8 +217,8 @@ class Oracle3:
 
     def __del__(self):
         h = getattr(self, "_h", None)
-        if h is not None and h.value:
-            lib().orc3_destroy(h)
+        if h is not None and h.value and _lib is not None:
+            _lib.orc3_destroy(h)
             self._h = None
 
     @property

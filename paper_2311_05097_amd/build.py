@@ -1,5 +1,6 @@
 """Build step of the HIP library: compiles csrc/lbm_abi.hip (which includes
-csrc/lbm_device.h) for gfx950 into liblbmgls.so next to this file."""
+csrc/lbm_device.h) and csrc/lbm3d.hip for gfx950 into liblbmgls.so next to
+this file."""
 from __future__ import annotations
 
 import os
@@ -9,6 +10,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 SRC = os.path.join(HERE, "csrc", "lbm_abi.hip")
+SRC3 = os.path.join(HERE, "csrc", "lbm3d.hip")
 OUT = os.path.join(HERE, "liblbmgls.so")
 
 HIPCC_FLAGS = [
@@ -32,7 +34,7 @@ def hipcc() -> str:
 
 def build(verbose: bool = False) -> str:
     tmp = OUT + ".tmp"
-    cmd = [hipcc(), *HIPCC_FLAGS, "-o", tmp, SRC]
+    cmd = [hipcc(), *HIPCC_FLAGS, "-o", tmp, SRC, SRC3]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.check_call(cmd)

@@ -1,0 +1,858 @@
+// lbm3d.hip -- three-dimensional path of the library (C ABI in lbmgls3d.h):
+// the phase-field and flow lattice Boltzmann models of Sec. 3.1-3.2 on a
+// 15-velocity lattice, four kernels per time step.
+//
+// Why four kernels and not one fused tile kernel as in two dimensions: the
+// node update needs the order parameter on a 3-node ring (mu needs its
+// Laplacian, the mass flux S the gradient of mu, F_c the divergence of a
+// tensor built from S).  In 3-D a 64 x 4 x 4 block would have to rebuild the
+// order parameter from 15 populations at ~7x as many ring nodes as it owns.
+// Instead the order parameter, mu and S are written once per step as FP64
+// planes (8 + 8 + 24 bytes per node) and read with their halos through the
+// caches.
+//
+// Layout (one domain, N = nx ny nz nodes, x fastest, planes of `pitch`
+// entries, pitch = N rounded up to 64):
+//   pop[2]  : 15 g planes then 15 f planes, storage type T (double or float);
+//             g_0 holds g_0 - phi_hist (the history order parameter stored
+//             at the same node) so that FP32 rounds only small numbers;
+//   hist[2] : phi, ux, uy, uz, Sx, Sy, Sz of the previous level, type T;
+//   stat    : phi0, psi = cos(theta) phi0, lap psi (FP64, built at creation);
+//   phi, mu, S (3): FP64 planes of the current level;
+//   out     : phi, ux, uy, uz, P (FP64) for reads;  part: per-block sums.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "lbmgls3d.h"
+
+namespace lbm3 {
+
+constexpr int Q = 15;
+constexpr int NT = 256;  // threads per block, one node each
+constexpr int NPART3 = 4;  // per-block sums: mass, E_F, E_K, non-finite count
+
+// Velocities: rest, the six faces, the eight corners.  This ordering is the
+// library's own: +x, +y, +z, -x, -y, -z, then the corners by sign pattern.
+__host__ __device__ constexpr int cxv(int i) {
+    return i == 0 ? 0 : (i <= 6 ? (i == 1 ? 1 : (i == 4 ? -1 : 0)) : (((i - 7) & 1) ? -1 : 1));
+}
+__host__ __device__ constexpr int cyv(int i) {
+    return i == 0 ? 0 : (i <= 6 ? (i == 2 ? 1 : (i == 5 ? -1 : 0)) : (((i - 7) & 2) ? -1 : 1));
+}
+__host__ __device__ constexpr int czv(int i) {
+    return i == 0 ? 0 : (i <= 6 ? (i == 3 ? 1 : (i == 6 ? -1 : 0)) : (((i - 7) & 4) ? -1 : 1));
+}
+
+// Hermite row k at velocity (x, y, z), cs2 = c_s^2 (c = 1).
+__host__ __device__ inline double hrow(int k, int x, int y, int z, double cs2) {
+    switch (k) {
+        case 0: return 1.0;
+        case 1: return x;
+        case 2: return y;
+        case 3: return z;
+        case 4: return x * x - cs2;
+        case 5: return y * y - cs2;
+        case 6: return z * z - cs2;
+        case 7: return x * y;
+        case 8: return x * z;
+        case 9: return y * z;
+        case 10: return x * (y * y - cs2);
+        case 11: return y * (z * z - cs2);
+        case 12: return z * (x * x - cs2);
+        case 13: return x * y * z;
+        default: return x * x * y * y - cs2 * (x * x + y * y + z * z) + 2.0 * cs2 * cs2;
+    }
+}
+
+struct Coef3 {
+    int32_t nx, ny, nz, first;  // first: the step at level 0 (u* = the given u, P = 0)
+    int64_t pitch, n;
+    double cs2, w[3], K, eta;   // weights: rest, face, corner
+    double sigma, Dw, Mob, rho1, rho2, mu1, mu2;
+    double gx, gy, gz, rho_ref, fbx, fby, fbz, solid_eps;
+    double sg[Q];               // phase-field rates
+    double s1, s3;              // flow rates of the first and third moments
+    double inv_norm[Q];         // 1 / sum_i w_i H_k(c_i)^2
+};
+
+template <class T>
+struct Planes3 {
+    T* pop[2];
+    T* hist[2];
+    double* stat;
+    double* phi;
+    double* mu;
+    double* S;
+    double* out;
+    double* part;
+};
+
+__device__ __forceinline__ double wgt(const Coef3& c, int i) { return i == 0 ? c.w[0] : (i <= 6 ? c.w[1] : c.w[2]); }
+
+// D3Q15 central-difference weights at c_s^2 = 1/3 (2/9, 1/9, 1/72).
+__device__ __forceinline__ double wfd(int i) { return i == 0 ? 2.0 / 9.0 : (i <= 6 ? 1.0 / 9.0 : 1.0 / 72.0); }
+
+struct Nb {
+    int64_t o[Q];  // node index of x + c_i, periodic
+};
+
+__device__ __forceinline__ void neighbours(const Coef3& c, int64_t o, Nb& nb) {
+    const int64_t nxy = (int64_t)c.nx * c.ny;
+    const int z = (int)(o / nxy);
+    const int64_t r = o - (int64_t)z * nxy;
+    const int y = (int)(r / c.nx), x = (int)(r - (int64_t)y * c.nx);
+    const int xs[3] = {x == 0 ? c.nx - 1 : x - 1, x, x == c.nx - 1 ? 0 : x + 1};
+    const int ys[3] = {y == 0 ? c.ny - 1 : y - 1, y, y == c.ny - 1 ? 0 : y + 1};
+    const int zs[3] = {z == 0 ? c.nz - 1 : z - 1, z, z == c.nz - 1 ? 0 : z + 1};
+#pragma unroll
+    for (int i = 0; i < Q; ++i)
+        nb.o[i] = ((int64_t)zs[czv(i) + 1] * c.ny + ys[cyv(i) + 1]) * c.nx + xs[cxv(i) + 1];
+}
+
+// finite: v - v is 0 for every finite v, NaN for NaN and +-Inf
+__device__ __forceinline__ bool fin(double v) { return v - v == 0.0; }
+
+__device__ __forceinline__ double rho_of(const Coef3& c, double ph) {
+    ph = ph < -1.0 ? -1.0 : (ph > 1.0 ? 1.0 : ph);
+    return c.rho2 + (c.rho1 - c.rho2) * (1.0 + ph) * 0.5;
+}
+
+__device__ __forceinline__ double muv_of(const Coef3& c, double ph) {
+    ph = ph < -1.0 ? -1.0 : (ph > 1.0 ? 1.0 : ph);
+    return c.mu2 + (c.mu1 - c.mu2) * (1.0 + ph) * 0.5;
+}
+
+// ---------------------------------------------------------------- statics
+// in: [0] phi0, [1] cos theta (staged FP64 inputs)
+__global__ __launch_bounds__(NT) void k3_static(Coef3 c, const double* __restrict__ in, double* __restrict__ stat) {
+    const int64_t o = (int64_t)blockIdx.x * NT + threadIdx.x;
+    if (o >= c.n) return;
+    double z = in[o];
+    z = z < 0.0 ? 0.0 : (z > 1.0 ? 1.0 : z);
+    stat[o] = z;
+    stat[c.pitch + o] = in[c.pitch + o] * z;
+}
+
+// lap psi from psi (FP64)
+__global__ __launch_bounds__(NT) void k3_lap_psi(Coef3 c, double* __restrict__ stat) {
+    const int64_t o = (int64_t)blockIdx.x * NT + threadIdx.x;
+    if (o >= c.n) return;
+    Nb nb;
+    neighbours(c, o, nb);
+    const double* psi = stat + c.pitch;
+    double s = 0.0;
+#pragma unroll
+    for (int i = 1; i < Q; ++i) s += wfd(i) * (psi[nb.o[i]] - psi[o]);
+    stat[2 * c.pitch + o] = 6.0 * s;
+}
+
+// ------------------------------------------------------ per-step kernels
+// Order parameter of the current level: phi = phi_hist + (g_0 - phi_hist)
+// + sum of the moving g_i.
+template <class T>
+__global__ __launch_bounds__(NT) void k3_phi(Coef3 c, Planes3<T> P, int cur) {
+    const int64_t o = (int64_t)blockIdx.x * NT + threadIdx.x;
+    if (o >= c.n) return;
+    const T* g = P.pop[cur];
+    double s = (double)P.hist[cur][o] + (double)g[o];
+#pragma unroll
+    for (int i = 1; i < Q; ++i) s += (double)g[(int64_t)i * c.pitch + o];
+    P.phi[o] = s;
+}
+
+// Eq. (potential): mu = (3 sigma/D) phi (phi^2 - 1) - (3 D sigma/8) lap phi
+// + (9 sigma/D) phi0^2 phi + (3 sigma/D) psi (3 phi^2 + phi0^2 - 1)
+// - (3 D sigma/8) lap psi
+template <class T>
+__global__ __launch_bounds__(NT) void k3_mu(Coef3 c, Planes3<T> P) {
+    const int64_t o = (int64_t)blockIdx.x * NT + threadIdx.x;
+    if (o >= c.n) return;
+    Nb nb;
+    neighbours(c, o, nb);
+    const double f = P.phi[o];
+    double lap = 0.0;
+#pragma unroll
+    for (int i = 1; i < Q; ++i) lap += wfd(i) * (P.phi[nb.o[i]] - f);
+    lap *= 6.0;
+    const double z = P.stat[o], q = P.stat[c.pitch + o], lq = P.stat[2 * c.pitch + o];
+    const double a = 3.0 * c.sigma / c.Dw, b = 3.0 * c.Dw * c.sigma / 8.0;
+    P.mu[o] = a * f * (f - 1.0) * (f + 1.0) - b * lap + 3.0 * a * z * z * f + a * q * (3.0 * f * f + z * z - 1.0) - b * lq;
+}
+
+// Consistent mass flux S = M grad(mu) (rho1 - rho2)/2.
+template <class T>
+__global__ __launch_bounds__(NT) void k3_flux(Coef3 c, Planes3<T> P) {
+    const int64_t o = (int64_t)blockIdx.x * NT + threadIdx.x;
+    if (o >= c.n) return;
+    Nb nb;
+    neighbours(c, o, nb);
+    double gx = 0.0, gy = 0.0, gz = 0.0;
+#pragma unroll
+    for (int i = 1; i < Q; ++i) {
+        const double v = wfd(i) * P.mu[nb.o[i]];
+        gx += cxv(i) * v;
+        gy += cyv(i) * v;
+        gz += czv(i) * v;
+    }
+    const double k = 3.0 * c.Mob * (c.rho1 - c.rho2) * 0.5;
+    P.S[o] = k * gx;
+    P.S[c.pitch + o] = k * gy;
+    P.S[2 * c.pitch + o] = k * gz;
+}
+
+enum { M3_STEP = 0, M3_OUT = 1 };
+
+// Block sum of NPART3 values in a fixed order (deterministic), thread 0 of
+// the block writes them.
+__device__ void block_sums(double v[NPART3], double* out) {
+    __shared__ double red[NPART3][NT];
+#pragma unroll
+    for (int k = 0; k < NPART3; ++k) red[k][threadIdx.x] = v[k];
+    __syncthreads();
+    for (int s = NT / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s)
+#pragma unroll
+            for (int k = 0; k < NPART3; ++k) red[k][threadIdx.x] += red[k][threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0)
+#pragma unroll
+        for (int k = 0; k < NPART3; ++k) out[(int64_t)blockIdx.x * NPART3 + k] = red[k][0];
+}
+
+// Node update of the current level (steps 4-6 and 2 of the procedure):
+// grad phi, grad rho, F_c, F, u*, the solid force, u, P, then in M3_STEP
+// both collisions, the push into the other copy and the history of this
+// level; in M3_OUT phi, u, P and the reductions.
+template <class T, int MODE>
+__global__ __launch_bounds__(NT) void k3_node(Coef3 c, Planes3<T> P, int cur) {
+    const int64_t o = (int64_t)blockIdx.x * NT + threadIdx.x;
+    const bool live = o < c.n;
+    double red[NPART3] = {0.0, 0.0, 0.0, 0.0};
+    if (live) {
+        Nb nb;
+        neighbours(c, o, nb);
+        const int64_t pt = c.pitch;
+        const T* H = P.hist[cur];
+        const double cs2 = c.cs2;
+        // ---- gradients of phi and rho, F_c = div(S u_lag - u_lag S)/2
+        const double ph = P.phi[o];
+        const double rho = rho_of(c, ph);
+        double dp[3] = {0.0, 0.0, 0.0}, dr[3] = {0.0, 0.0, 0.0}, fc[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+        for (int i = 1; i < Q; ++i) {
+            const int64_t n = nb.o[i];
+            const double wi = wfd(i);
+            const double pn = P.phi[n], rn = rho_of(c, pn);
+            const double ci[3] = {(double)cxv(i), (double)cyv(i), (double)czv(i)};
+            const double Sn[3] = {P.S[n], P.S[pt + n], P.S[2 * pt + n]};
+            const double un[3] = {(double)H[pt + n], (double)H[2 * pt + n], (double)H[3 * pt + n]};
+            const double cS = ci[0] * Sn[0] + ci[1] * Sn[1] + ci[2] * Sn[2];
+            const double cu = ci[0] * un[0] + ci[1] * un[1] + ci[2] * un[2];
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                dp[a] += wi * ci[a] * pn;
+                dr[a] += wi * ci[a] * rn;
+                fc[a] += wi * (cS * un[a] - cu * Sn[a]);
+            }
+        }
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            dp[a] *= 3.0;
+            dr[a] *= 3.0;
+            fc[a] *= 1.5;  // 3 (1/c_s^2) x 1/2
+        }
+        const double mu = P.mu[o];
+        const double S[3] = {P.S[o], P.S[pt + o], P.S[2 * pt + o]};
+        const double z = P.stat[o];
+        const double F[3] = {mu * dp[0] + (rho - c.rho_ref) * c.gx + (1.0 - z) * c.fbx + fc[0],
+                             mu * dp[1] + (rho - c.rho_ref) * c.gy + (1.0 - z) * c.fby + fc[1],
+                             mu * dp[2] + (rho - c.rho_ref) * c.gz + (1.0 - z) * c.fbz + fc[2]};
+        // ---- history of the previous level
+        const double php = (double)H[o];
+        const double up[3] = {(double)H[pt + o], (double)H[2 * pt + o], (double)H[3 * pt + o]};
+        const double Sp[3] = {(double)H[4 * pt + o], (double)H[5 * pt + o], (double)H[6 * pt + o]};
+        // ---- flow populations
+        const T* gp = P.pop[cur];
+        const T* fp = gp + (int64_t)Q * pt;
+        double f[Q];
+#pragma unroll
+        for (int i = 0; i < Q; ++i) f[i] = (double)fp[(int64_t)i * pt + o];
+        // ---- viscosity: nu = (1/s2a - 1/2)(1 - c_s^2)/2 = (1/s2b - 1/2) c_s^2
+        double om = 1.0 - z;
+        om = om < c.solid_eps ? c.solid_eps : om;
+        const double nu = muv_of(c, ph) / (rho * om);
+        const double ta = nu / ((1.0 - cs2) * 0.5) + 0.5, tb = nu / cs2 + 0.5;
+        const double s2a = 1.0 / ta, s2b = 1.0 / tb;
+        // ---- u*, solid force, u, P (Eqs. uStar, u)
+        double us[3], af[3], u[3];
+        if (c.first) {
+#pragma unroll
+            for (int a = 0; a < 3; ++a) us[a] = up[a];
+        } else {
+            double j[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+            for (int i = 1; i < Q; ++i) {
+                j[0] += cxv(i) * f[i];
+                j[1] += cyv(i) * f[i];
+                j[2] += czv(i) * f[i];
+            }
+#pragma unroll
+            for (int a = 0; a < 3; ++a) us[a] = (j[a] + 0.5 * F[a]) / rho;
+        }
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            af[a] = -z * us[a];  // phi0 (u_s - u*) with u_s = 0
+            u[a] = c.first ? us[a] : us[a] + 0.5 * af[a];
+        }
+        const double udr = u[0] * dr[0] + u[1] * dr[1] + u[2] * dr[2];
+        const double Su = S[0] * u[0] + S[1] * u[1] + S[2] * u[2];
+        const double q = rho * (u[0] * u[0] + u[1] * u[1] + u[2] * u[2]) - Su;
+        const double rhop = rho_of(c, php);
+        const double qp = rhop * (up[0] * up[0] + up[1] * up[1] + up[2] * up[2]) -
+                          (Sp[0] * up[0] + Sp[1] * up[1] + Sp[2] * up[2]);
+        double Pr = 0.0;
+        if (!c.first) {
+            double sum = 0.0;
+#pragma unroll
+            for (int i = 1; i < Q; ++i) sum += f[i];
+            // H = -2 K (1 - 3 d0)(1/s2a - 1/2) (the printed 3-D factor with s0 = s2a)
+            const double Hf = -2.0 * c.K * (1.0 - 3.0 * cs2) * (ta - 0.5);
+            Pr = cs2 / (1.0 - c.w[0]) *
+                 (sum + (0.5 + Hf) * udr - c.w[0] * (rho * (u[0] * u[0] + u[1] * u[1] + u[2] * u[2]) - Su) / (1.0 - cs2) +
+                  0.5 * c.K * (q - qp));
+        }
+        if (MODE == M3_OUT) {
+            double* out = P.out;
+            out[o] = ph;
+            out[pt + o] = u[0];
+            out[2 * pt + o] = u[1];
+            out[3 * pt + o] = u[2];
+            out[4 * pt + o] = Pr;
+            // Eq. (2energy) with psi; grad psi from the static plane
+            const double* psi = P.stat + pt;
+            double gq[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+            for (int i = 1; i < Q; ++i) {
+                const double v = wfd(i) * psi[nb.o[i]];
+                gq[0] += cxv(i) * v;
+                gq[1] += cyv(i) * v;
+                gq[2] += czv(i) * v;
+            }
+            const double qq = psi[o], s = c.sigma, D = c.Dw;
+            const double g2 = dp[0] * dp[0] + dp[1] * dp[1] + dp[2] * dp[2];
+            const double gpq = 3.0 * (gq[0] * dp[0] + gq[1] * dp[1] + gq[2] * dp[2]);
+            red[0] = ph;
+            red[1] = 3.0 * s / (4.0 * D) * (1.0 - ph) * (1.0 - ph) * (1.0 + ph) * (1.0 + ph) + 3.0 * D * s / 16.0 * g2 +
+                     9.0 * s / (2.0 * D) * z * z * ph * ph + 3.0 * s / D * qq * ph * (ph * ph + z * z - 1.0) +
+                     3.0 * D * s / 8.0 * gpq;
+            red[2] = 0.5 * rho * (u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
+            red[3] = (fin(ph) && fin(u[0]) && fin(u[1]) && fin(u[2]) && fin(Pr)) ? 0.0 : 1.0;
+        } else {
+            const int nxt = cur ^ 1;
+            T* gn = P.pop[nxt];
+            T* fn = gn + (int64_t)Q * pt;
+            // ---- flow collision in Hermite moments: dm_k = -s_k (m_k - m_k^eq) + (1 - s_k/2) F_k,
+            // f* = f + w_i sum_k H_k(c_i) dm_k / |H_k|^2
+            const int A6[6] = {0, 1, 2, 0, 0, 1}, B6[6] = {0, 1, 2, 1, 2, 2};
+            double M2[6];
+#pragma unroll
+            for (int k = 0; k < 6; ++k) {
+                const int a = A6[k], b = B6[k];
+                const double T_now = 0.5 * (S[a] * u[b] + u[a] * S[b]);
+                const double T_old = 0.5 * (Sp[a] * up[b] + up[a] * Sp[b]);
+                M2[k] = (u[a] * F[b] + F[a] * u[b]) - (T_now - T_old) + cs2 * (u[a] * dr[b] + dr[a] * u[b]) +
+                        (a == b ? (1.0 - 3.0 * cs2) * udr : 0.0);
+            }
+            double m[Q];
+#pragma unroll
+            for (int k = 0; k < Q; ++k) {
+                double s = 0.0;
+#pragma unroll
+                for (int i = 0; i < Q; ++i) s += hrow(k, cxv(i), cyv(i), czv(i), cs2) * f[i];
+                m[k] = s;
+            }
+            double meq[Q], src[Q], rate[Q];
+            const double r2 = rho * 1.0;
+            meq[0] = 0.0;
+            src[0] = udr;
+            rate[0] = s2a;
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                meq[1 + a] = r2 * u[a];
+                src[1 + a] = F[a] + rho * af[a];
+                rate[1 + a] = c.s1;
+                meq[4 + a] = Pr + rho * u[a] * u[a] - S[a] * u[a];
+                src[4 + a] = M2[a];
+                rate[4 + a] = s2a;
+            }
+            meq[7] = rho * u[0] * u[1] - 0.5 * (S[0] * u[1] + u[0] * S[1]);
+            meq[8] = rho * u[0] * u[2] - 0.5 * (S[0] * u[2] + u[0] * S[2]);
+            meq[9] = rho * u[1] * u[2] - 0.5 * (S[1] * u[2] + u[1] * S[2]);
+            src[7] = M2[3];
+            src[8] = M2[4];
+            src[9] = M2[5];
+            rate[7] = rate[8] = rate[9] = s2b;
+#pragma unroll
+            for (int k = 10; k < 14; ++k) {
+                meq[k] = 0.0;
+                src[k] = 0.0;
+                rate[k] = c.s3;
+            }
+            meq[14] = -2.0 * cs2 * Pr;
+            src[14] = 0.0;
+            rate[14] = s2a;
+            double dm[Q];
+#pragma unroll
+            for (int k = 0; k < Q; ++k) dm[k] = (-rate[k] * (m[k] - meq[k]) + (1.0 - 0.5 * rate[k]) * src[k]) * c.inv_norm[k];
+#pragma unroll
+            for (int i = 0; i < Q; ++i) {
+                double s = 0.0;
+#pragma unroll
+                for (int k = 0; k < Q; ++k) s += hrow(k, cxv(i), cyv(i), czv(i), cs2) * dm[k];
+                fn[(int64_t)i * pt + nb.o[i]] = (T)(f[i] + wgt(c, i) * s);
+            }
+            // ---- phase-field collision (Sec. 3.1)
+            double g[Q];
+            g[0] = php + (double)gp[o];
+#pragma unroll
+            for (int i = 1; i < Q; ++i) g[i] = (double)gp[(int64_t)i * pt + o];
+            double mg[Q];
+#pragma unroll
+            for (int k = 0; k < Q; ++k) {
+                double s = 0.0;
+#pragma unroll
+                for (int i = 0; i < Q; ++i) s += hrow(k, cxv(i), cyv(i), czv(i), cs2) * g[i];
+                mg[k] = s;
+            }
+            const double em = c.eta * mu;
+            double geq[Q], gsrc[Q];
+            geq[0] = ph;
+            gsrc[0] = 0.0;
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                geq[1 + a] = ph * u[a];
+                gsrc[1 + a] = ph * u[a] - php * up[a];  // d_t(phi u), backward difference
+                geq[4 + a] = -cs2 * (ph - em);
+                gsrc[4 + a] = 0.0;
+            }
+#pragma unroll
+            for (int k = 7; k < 14; ++k) {
+                geq[k] = 0.0;
+                gsrc[k] = 0.0;
+            }
+            geq[14] = 2.0 * cs2 * cs2 * (ph - em);
+            gsrc[14] = 0.0;
+#pragma unroll
+            for (int k = 0; k < Q; ++k)
+                dm[k] = (-c.sg[k] * (mg[k] - geq[k]) + (1.0 - 0.5 * c.sg[k]) * gsrc[k]) * c.inv_norm[k];
+            const T phs = (T)ph;  // the history value g_0 is stored against
+#pragma unroll
+            for (int i = 0; i < Q; ++i) {
+                double s = 0.0;
+#pragma unroll
+                for (int k = 0; k < Q; ++k) s += hrow(k, cxv(i), cyv(i), czv(i), cs2) * dm[k];
+                const double gi = g[i] + wgt(c, i) * s;
+                if (i == 0)
+                    gn[o] = (T)(gi - (double)phs);
+                else
+                    gn[(int64_t)i * pt + nb.o[i]] = (T)gi;
+            }
+            // ---- history of this level
+            T* Hn = P.hist[nxt];
+            Hn[o] = phs;
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                Hn[(1 + a) * pt + o] = (T)u[a];
+                Hn[(4 + a) * pt + o] = (T)S[a];
+            }
+        }
+    }
+    if (MODE == M3_OUT) block_sums(red, P.part);
+}
+
+// Equilibria of the initial state (procedure step 1): g = g^eq(phi, mu, u),
+// f = f^eq(P = 0, rho, u, S), history = (phi, u, S); u from the staged input.
+template <class T>
+__global__ __launch_bounds__(NT) void k3_equilibrium(Coef3 c, Planes3<T> P, const double* __restrict__ uin) {
+    const int64_t o = (int64_t)blockIdx.x * NT + threadIdx.x;
+    if (o >= c.n) return;
+    const int64_t pt = c.pitch;
+    const double cs2 = c.cs2;
+    const double ph = P.phi[o], rho = rho_of(c, ph), em = c.eta * P.mu[o];
+    const double u[3] = {uin[o], uin[pt + o], uin[2 * pt + o]};
+    const double S[3] = {P.S[o], P.S[pt + o], P.S[2 * pt + o]};
+    T* g = P.pop[0];
+    T* f = g + (int64_t)Q * pt;
+    const T phs = (T)ph;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        const double ci[3] = {(double)cxv(i), (double)cyv(i), (double)czv(i)};
+        const double w = wgt(c, i);
+        const double cu = ci[0] * u[0] + ci[1] * u[1] + ci[2] * u[2];
+        // Sec. 3.1
+        const double gi = (i == 0 ? ph + (w - 1.0) * em : w * em) + w * ph * cu / cs2;
+        // Sec. 3.2 with P = 0
+        double diag = 0.0;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) diag += (ci[a] * ci[a] - cs2) * (rho * u[a] * u[a] - S[a] * u[a]);
+        diag /= cs2 - cs2 * cs2;
+        const double off = (ci[0] * ci[1] * (rho * u[0] * u[1] - 0.5 * (S[0] * u[1] + u[0] * S[1])) +
+                            ci[0] * ci[2] * (rho * u[0] * u[2] - 0.5 * (S[0] * u[2] + u[0] * S[2])) +
+                            ci[1] * ci[2] * (rho * u[1] * u[2] - 0.5 * (S[1] * u[2] + u[1] * S[2]))) /
+                           (cs2 * cs2);
+        const double fi = w * rho * cu / cs2 + w * (diag + off);
+        g[(int64_t)i * pt + o] = (T)(i == 0 ? gi - (double)phs : gi);
+        f[(int64_t)i * pt + o] = (T)fi;
+    }
+    T* H = P.hist[0];
+    H[o] = phs;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        H[(1 + a) * pt + o] = (T)u[a];
+        H[(4 + a) * pt + o] = (T)S[a];
+    }
+}
+
+}  // namespace lbm3
+
+using namespace lbm3;
+
+struct lbm3_domain {
+    lbm3_params p{};
+    Coef3 c{};
+    hipStream_t stream = nullptr;
+    char* ws = nullptr;
+    int cur = 0;
+    int64_t steps = 0;
+    int64_t blocks = 0;
+    int64_t timed_steps = 0;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    size_t off_pop[2]{}, off_hist[2]{}, off_stat = 0, off_phi = 0, off_mu = 0, off_S = 0, off_out = 0, off_part = 0;
+};
+
+namespace {
+
+thread_local std::string g_err3;
+
+int fail3(int code, const std::string& msg) {
+    g_err3 = msg;
+    return code;
+}
+
+#define HIPCHK3(x)                                                                         \
+    do {                                                                                   \
+        hipError_t e_ = (x);                                                               \
+        if (e_ != hipSuccess)                                                              \
+            return fail3(LBM_EDEVICE, std::string(#x) + ": " + hipGetErrorString(e_));      \
+    } while (0)
+
+size_t up256(size_t v) { return (v + 255) / 256 * 256; }
+
+int validate3(const lbm3_params* p) {
+    if (!p) return fail3(LBM_EINVAL, "params is NULL");
+    if (p->nx < 3 || p->ny < 3 || p->nz < 3) return fail3(LBM_EINVAL, "nx, ny, nz must be >= 3");
+    if ((int64_t)p->nx * p->ny * p->nz > (int64_t)1 << 31) return fail3(LBM_EINVAL, "more than 2^31 nodes");
+    if (p->storage != LBM_STORE_FP64 && p->storage != LBM_STORE_FP32)
+        return fail3(LBM_EUNSUPPORTED, "3-D storage must be LBM_STORE_FP64 or LBM_STORE_FP32");
+    const double v[] = {p->d0, p->sigma, p->D, p->M, p->rho1, p->rho2, p->mu1, p->mu2, p->tau_phi, p->s0, p->s1,
+                        p->s2, p->s3, p->s4, p->gx, p->gy, p->gz, p->rho_ref, p->fbx, p->fby, p->fbz, p->solid_eps};
+    for (double x : v)
+        if (!std::isfinite(x)) return fail3(LBM_EINVAL, "non-finite parameter");
+    if (!(p->d0 > 0.0 && p->d0 < 0.5)) return fail3(LBM_EINVAL, "d0 must be in (0, 1/2)");
+    if (!(p->D > 0.0) || !(p->M > 0.0) || !(p->sigma >= 0.0)) return fail3(LBM_EINVAL, "D, M must be > 0, sigma >= 0");
+    if (!(p->rho1 > 0.0 && p->rho2 > 0.0 && p->mu1 > 0.0 && p->mu2 > 0.0))
+        return fail3(LBM_EINVAL, "densities and viscosities must be > 0");
+    if (!(p->tau_phi > 0.5)) return fail3(LBM_EINVAL, "tau_phi must be > 1/2");
+    const double s[] = {p->s0, p->s1, p->s2, p->s3, p->s4};
+    for (double x : s)
+        if (!(x > 0.0 && x < 2.0)) return fail3(LBM_EINVAL, "relaxation rates must be in (0, 2)");
+    if (!(p->solid_eps > 0.0 && p->solid_eps <= 1.0)) return fail3(LBM_EINVAL, "solid_eps must be in (0, 1]");
+    return LBM_OK;
+}
+
+struct Sizes3 {
+    int64_t n, pitch, blocks;
+    size_t pop, hist, total;
+    size_t off_pop[2], off_hist[2], off_stat, off_phi, off_mu, off_S, off_out, off_part;
+};
+
+Sizes3 sizes3(const lbm3_params& p) {
+    Sizes3 s{};
+    s.n = (int64_t)p.nx * p.ny * p.nz;
+    s.pitch = (s.n + 63) / 64 * 64;
+    s.blocks = (s.n + NT - 1) / NT;
+    const size_t r = p.storage == LBM_STORE_FP64 ? 8 : 4;
+    s.pop = up256((size_t)2 * Q * s.pitch * r);
+    s.hist = up256((size_t)7 * s.pitch * r);
+    size_t o = 0;
+    for (int k = 0; k < 2; ++k) { s.off_pop[k] = o; o += s.pop; }
+    for (int k = 0; k < 2; ++k) { s.off_hist[k] = o; o += s.hist; }
+    s.off_stat = o; o += up256((size_t)3 * s.pitch * 8);
+    s.off_phi = o; o += up256((size_t)s.pitch * 8);
+    s.off_mu = o; o += up256((size_t)s.pitch * 8);
+    s.off_S = o; o += up256((size_t)3 * s.pitch * 8);
+    s.off_out = o; o += up256((size_t)5 * s.pitch * 8);
+    s.off_part = o; o += up256((size_t)s.blocks * NPART3 * 8);
+    s.total = o;
+    return s;
+}
+
+void fill_coef3(const lbm3_params& p, const Sizes3& z, Coef3& c) {
+    const double d0 = p.d0, cs2 = d0;
+    c.nx = p.nx; c.ny = p.ny; c.nz = p.nz; c.first = 1;
+    c.pitch = z.pitch; c.n = z.n;
+    c.cs2 = cs2;
+    c.w[0] = (1.0 - d0) * (1.0 - 2.0 * d0);
+    c.w[1] = (d0 - d0 * d0) / 2.0;
+    c.w[2] = d0 * d0 / 8.0;
+    c.K = 1.0 - 2.0 * d0;
+    c.eta = p.M / ((p.tau_phi - 0.5) * cs2);  // M = (1/s_1phi - 1/2) eta c_s^2
+    c.sigma = p.sigma; c.Dw = p.D; c.Mob = p.M;
+    c.rho1 = p.rho1; c.rho2 = p.rho2; c.mu1 = p.mu1; c.mu2 = p.mu2;
+    c.gx = p.gx; c.gy = p.gy; c.gz = p.gz; c.rho_ref = p.rho_ref;
+    c.fbx = p.fbx; c.fby = p.fby; c.fbz = p.fbz; c.solid_eps = p.solid_eps;
+    const double s1p = 1.0 / p.tau_phi;
+    const double sg[Q] = {p.s0, s1p, s1p, s1p, p.s2, p.s2, p.s2, p.s2, p.s2, p.s2, p.s3, p.s3, p.s3, p.s3, p.s4};
+    for (int k = 0; k < Q; ++k) c.sg[k] = sg[k];
+    c.s1 = p.s1; c.s3 = p.s3;
+    // norms of the Hermite rows under the weights
+    for (int k = 0; k < Q; ++k) {
+        double s = 0.0;
+        for (int i = 0; i < Q; ++i) {
+            const double w = i == 0 ? c.w[0] : (i <= 6 ? c.w[1] : c.w[2]);
+            const double h = hrow(k, cxv(i), cyv(i), czv(i), cs2);
+            s += w * h * h;
+        }
+        c.inv_norm[k] = 1.0 / s;
+    }
+}
+
+template <class T>
+Planes3<T> planes(lbm3_domain* d) {
+    Planes3<T> P{};
+    for (int k = 0; k < 2; ++k) {
+        P.pop[k] = (T*)(d->ws + d->off_pop[k]);
+        P.hist[k] = (T*)(d->ws + d->off_hist[k]);
+    }
+    P.stat = (double*)(d->ws + d->off_stat);
+    P.phi = (double*)(d->ws + d->off_phi);
+    P.mu = (double*)(d->ws + d->off_mu);
+    P.S = (double*)(d->ws + d->off_S);
+    P.out = (double*)(d->ws + d->off_out);
+    P.part = (double*)(d->ws + d->off_part);
+    return P;
+}
+
+// phi of the current level from the populations, then mu and S
+template <class T>
+int fields3(lbm3_domain* d) {
+    Planes3<T> P = planes<T>(d);
+    const dim3 g((unsigned)d->blocks), b(NT);
+    hipLaunchKernelGGL(k3_phi<T>, g, b, 0, d->stream, d->c, P, d->cur);
+    hipLaunchKernelGGL(k3_mu<T>, g, b, 0, d->stream, d->c, P);
+    hipLaunchKernelGGL(k3_flux<T>, g, b, 0, d->stream, d->c, P);
+    HIPCHK3(hipGetLastError());
+    return LBM_OK;
+}
+
+template <class T>
+int step3(lbm3_domain* d, int64_t nsteps) {
+    HIPCHK3(hipEventRecord(d->ev0, d->stream));
+    for (int64_t s = 0; s < nsteps; ++s) {
+        int rc = fields3<T>(d);
+        if (rc) return rc;
+        Planes3<T> P = planes<T>(d);
+        hipLaunchKernelGGL((k3_node<T, M3_STEP>), dim3((unsigned)d->blocks), dim3(NT), 0, d->stream, d->c, P, d->cur);
+        HIPCHK3(hipGetLastError());
+        d->cur ^= 1;
+        d->c.first = 0;
+        d->steps++;
+    }
+    HIPCHK3(hipEventRecord(d->ev1, d->stream));
+    d->timed_steps = nsteps;
+    return LBM_OK;
+}
+
+// macroscopic pass of the current level into `out` and the block sums
+template <class T>
+int out3(lbm3_domain* d, double res[NPART3]) {
+    int rc = fields3<T>(d);
+    if (rc) return rc;
+    Planes3<T> P = planes<T>(d);
+    hipLaunchKernelGGL((k3_node<T, M3_OUT>), dim3((unsigned)d->blocks), dim3(NT), 0, d->stream, d->c, P, d->cur);
+    HIPCHK3(hipGetLastError());
+    std::vector<double> part((size_t)d->blocks * NPART3);
+    HIPCHK3(hipMemcpyAsync(part.data(), P.part, part.size() * 8, hipMemcpyDeviceToHost, d->stream));
+    HIPCHK3(hipStreamSynchronize(d->stream));
+    for (int k = 0; k < NPART3; ++k) res[k] = 0.0;
+    for (int64_t b = 0; b < d->blocks; ++b)
+        for (int k = 0; k < NPART3; ++k) res[k] += part[(size_t)b * NPART3 + k];
+    return LBM_OK;
+}
+
+template <class T>
+int create3(lbm3_domain* d, const double* phi, const double* phi0, const double* cth, const double* ux,
+            const double* uy, const double* uz) {
+    Planes3<T> P = planes<T>(d);
+    const int64_t n = d->c.n, pt = d->c.pitch;
+    const dim3 g((unsigned)d->blocks), b(NT);
+    // stage: out[0] phi0, out[1] cos theta, out[2..4] u (FP64)
+    double* st = P.out;
+    std::vector<double> tmp((size_t)n, 0.0);
+    HIPCHK3(hipMemcpyAsync(st, phi0, n * 8, hipMemcpyHostToDevice, d->stream));
+    HIPCHK3(hipMemcpyAsync(st + pt, cth ? cth : tmp.data(), n * 8, hipMemcpyHostToDevice, d->stream));
+    const double* us[3] = {ux, uy, uz};
+    for (int a = 0; a < 3; ++a)
+        HIPCHK3(hipMemcpyAsync(st + (2 + a) * pt, us[a] ? us[a] : tmp.data(), n * 8, hipMemcpyHostToDevice, d->stream));
+    HIPCHK3(hipMemcpyAsync(P.phi, phi, n * 8, hipMemcpyHostToDevice, d->stream));
+    hipLaunchKernelGGL(k3_static, g, b, 0, d->stream, d->c, (const double*)st, P.stat);
+    hipLaunchKernelGGL(k3_lap_psi, g, b, 0, d->stream, d->c, P.stat);
+    hipLaunchKernelGGL(k3_mu<T>, g, b, 0, d->stream, d->c, P);
+    hipLaunchKernelGGL(k3_flux<T>, g, b, 0, d->stream, d->c, P);
+    hipLaunchKernelGGL(k3_equilibrium<T>, g, b, 0, d->stream, d->c, P, (const double*)(st + 2 * pt));
+    HIPCHK3(hipGetLastError());
+    HIPCHK3(hipStreamSynchronize(d->stream));  // tmp must outlive the copies
+    d->cur = 0;
+    d->c.first = 1;
+    return LBM_OK;
+}
+
+template <class F>
+int dispatch3(int storage, F&& f) {
+    if (storage == LBM_STORE_FP64) return f(double{});
+    return f(float{});
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* lbm3_last_error(void) { return g_err3.c_str(); }
+
+void lbm3_default_params(lbm3_params* p, int32_t nx, int32_t ny, int32_t nz) {
+    if (!p) return;
+    std::memset(p, 0, sizeof *p);
+    p->nx = nx; p->ny = ny; p->nz = nz;
+    p->storage = LBM_STORE_FP64;
+    p->d0 = 0.4; p->sigma = 1e-3; p->D = 4.0; p->M = 0.1;
+    p->rho1 = p->rho2 = 1.0; p->mu1 = p->mu2 = 0.1;
+    p->tau_phi = 1.0;
+    p->s0 = p->s1 = p->s2 = p->s3 = p->s4 = 1.0;
+    p->solid_eps = 0.01;
+}
+
+size_t lbm3_workspace_bytes(const lbm3_params* p) {
+    if (validate3(p)) return 0;
+    return sizes3(*p).total;
+}
+
+int lbm3_create(const lbm3_params* p, void* dev_workspace, size_t bytes, void* hip_stream, const double* phi,
+                const double* phi0, const double* cos_theta, const double* ux, const double* uy, const double* uz,
+                lbm3_domain** out) {
+    if (!out) return fail3(LBM_EINVAL, "out is NULL");
+    *out = nullptr;
+    int rc = validate3(p);
+    if (rc) return rc;
+    if (!phi || !phi0) return fail3(LBM_EINVAL, "phi and phi0 are required");
+    if (!dev_workspace || ((uintptr_t)dev_workspace & 255)) return fail3(LBM_EINVAL, "workspace NULL or not 256-byte aligned");
+    const Sizes3 z = sizes3(*p);
+    if (bytes < z.total) return fail3(LBM_ENOMEM, "workspace too small: need " + std::to_string(z.total) + " bytes");
+    for (int64_t o = 0; o < z.n; ++o) {
+        if (!std::isfinite(phi[o]) || !std::isfinite(phi0[o]) || (cos_theta && !(std::fabs(cos_theta[o]) <= 1.0)) ||
+            (ux && !std::isfinite(ux[o])) || (uy && !std::isfinite(uy[o])) || (uz && !std::isfinite(uz[o])))
+            return fail3(LBM_EINVAL, "non-finite or out-of-range input at node " + std::to_string(o));
+    }
+    lbm3_domain* d = new lbm3_domain();
+    d->p = *p;
+    d->stream = (hipStream_t)hip_stream;
+    d->ws = (char*)dev_workspace;
+    d->blocks = z.blocks;
+    for (int k = 0; k < 2; ++k) {
+        d->off_pop[k] = z.off_pop[k];
+        d->off_hist[k] = z.off_hist[k];
+    }
+    d->off_stat = z.off_stat; d->off_phi = z.off_phi; d->off_mu = z.off_mu; d->off_S = z.off_S;
+    d->off_out = z.off_out; d->off_part = z.off_part;
+    fill_coef3(*p, z, d->c);
+    if (hipEventCreate(&d->ev0) != hipSuccess || hipEventCreate(&d->ev1) != hipSuccess) {
+        lbm3_destroy(d);
+        return fail3(LBM_EDEVICE, "hipEventCreate failed");
+    }
+    rc = dispatch3(p->storage, [&](auto s) { return create3<decltype(s)>(d, phi, phi0, cos_theta, ux, uy, uz); });
+    if (rc) {
+        lbm3_destroy(d);
+        return rc;
+    }
+    *out = d;
+    return LBM_OK;
+}
+
+int lbm3_step(lbm3_domain* d, int64_t nsteps) {
+    if (!d) return fail3(LBM_EINVAL, "domain is NULL");
+    if (nsteps < 0) return fail3(LBM_EINVAL, "nsteps must be >= 0");
+    if (nsteps == 0) return LBM_OK;
+    return dispatch3(d->p.storage, [&](auto s) { return step3<decltype(s)>(d, nsteps); });
+}
+
+int lbm3_read(lbm3_domain* d, double* phi, double* ux, double* uy, double* uz, double* p) {
+    if (!d) return fail3(LBM_EINVAL, "domain is NULL");
+    return dispatch3(d->p.storage, [&](auto s) -> int {
+        double res[NPART3];
+        int rc = out3<decltype(s)>(d, res);
+        if (rc) return rc;
+        const double* o = (const double*)(d->ws + d->off_out);
+        double* dst[5] = {phi, ux, uy, uz, p};
+        for (int k = 0; k < 5; ++k)
+            if (dst[k]) HIPCHK3(hipMemcpyAsync(dst[k], o + k * d->c.pitch, d->c.n * 8, hipMemcpyDeviceToHost, d->stream));
+        HIPCHK3(hipStreamSynchronize(d->stream));
+        if (res[3] > 0.0) return fail3(LBM_ENONFINITE, "non-finite phi, u or P at step " + std::to_string(d->steps));
+        return LBM_OK;
+    });
+}
+
+int lbm3_mass(lbm3_domain* d, double* sum_phi) {
+    if (!d || !sum_phi) return fail3(LBM_EINVAL, "domain or sum_phi is NULL");
+    return dispatch3(d->p.storage, [&](auto s) -> int {
+        double res[NPART3];
+        int rc = out3<decltype(s)>(d, res);
+        if (rc) return rc;
+        *sum_phi = res[0];
+        return LBM_OK;
+    });
+}
+
+int lbm3_energy(lbm3_domain* d, double* e_free, double* e_kin) {
+    if (!d) return fail3(LBM_EINVAL, "domain is NULL");
+    return dispatch3(d->p.storage, [&](auto s) -> int {
+        double res[NPART3];
+        int rc = out3<decltype(s)>(d, res);
+        if (rc) return rc;
+        if (e_free) *e_free = res[1];
+        if (e_kin) *e_kin = res[2];
+        return LBM_OK;
+    });
+}
+
+double lbm3_last_step_ms(const lbm3_domain* d) {
+    if (!d || d->timed_steps <= 0) return 0.0;
+    if (hipEventSynchronize(d->ev1) != hipSuccess) return 0.0;
+    float ms = 0.0f;
+    if (hipEventElapsedTime(&ms, d->ev0, d->ev1) != hipSuccess) return 0.0;
+    return (double)ms / (double)d->timed_steps;
+}
+
+int lbm3_destroy(lbm3_domain* d) {
+    if (!d) return LBM_OK;
+    if (d->stream || d->ev1) (void)hipStreamSynchronize(d->stream);
+    if (d->ev0) (void)hipEventDestroy(d->ev0);
+    if (d->ev1) (void)hipEventDestroy(d->ev1);
+    delete d;
+    return LBM_OK;
+}
+
+}  // extern "C"

@@ -30,6 +30,10 @@ EXPORTED = [
     "lbm_smooth_solid_noalloc",
 ]
 NOALLOC_MAX_NODES = 1 << 18  # LBM_NOALLOC_MAX_NODES of include/lbmgls.h
+EXPORTED_3D = [  # include/lbmgls3d.h
+    "lbm3_last_error", "lbm3_default_params", "lbm3_workspace_bytes", "lbm3_create", "lbm3_step",
+    "lbm3_read", "lbm3_mass", "lbm3_energy", "lbm3_last_step_ms", "lbm3_destroy",
+]
 
 
 class LbmError(RuntimeError):
@@ -57,6 +61,20 @@ class LbmParams(ctypes.Structure):
     ]
 
 
+class Lbm3Params(ctypes.Structure):
+    _fields_ = [
+        ("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32), ("storage", ctypes.c_int32),
+        ("d0", ctypes.c_double), ("sigma", ctypes.c_double), ("D", ctypes.c_double), ("M", ctypes.c_double),
+        ("rho1", ctypes.c_double), ("rho2", ctypes.c_double), ("mu1", ctypes.c_double), ("mu2", ctypes.c_double),
+        ("tau_phi", ctypes.c_double),
+        ("s0", ctypes.c_double), ("s1", ctypes.c_double), ("s2", ctypes.c_double), ("s3", ctypes.c_double),
+        ("s4", ctypes.c_double),
+        ("gx", ctypes.c_double), ("gy", ctypes.c_double), ("gz", ctypes.c_double), ("rho_ref", ctypes.c_double),
+        ("fbx", ctypes.c_double), ("fby", ctypes.c_double), ("fbz", ctypes.c_double),
+        ("solid_eps", ctypes.c_double),
+    ]
+
+
 _lib = None
 _D = ctypes.POINTER(ctypes.c_double)
 _VP = ctypes.c_void_p
@@ -75,6 +93,7 @@ def lib():
             _torch()
         L = ctypes.CDLL(LIB_PATH)
         P = ctypes.POINTER(LbmParams)
+        P3 = ctypes.POINTER(Lbm3Params)
         sig = {
             "lbm_default_params": (None, [P, ctypes.c_int32, ctypes.c_int32]),
             "lbm_workspace_bytes": (ctypes.c_size_t, [P]),
@@ -109,6 +128,17 @@ def lib():
             "lbm_smooth_solid": (ctypes.c_int, [P, ctypes.c_int32, ctypes.c_double, _VP, ctypes.c_size_t, _VP,
                                                 _D, _D]),
             "lbm_smooth_solid_noalloc": (ctypes.c_int, [P, ctypes.c_int32, ctypes.c_double, _VP, _D, _D]),
+            "lbm3_last_error": (ctypes.c_char_p, []),
+            "lbm3_default_params": (None, [P3, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]),
+            "lbm3_workspace_bytes": (ctypes.c_size_t, [P3]),
+            "lbm3_create": (ctypes.c_int, [P3, _VP, ctypes.c_size_t, _VP, _D, _D, _D, _D, _D, _D,
+                                           ctypes.POINTER(_VP)]),
+            "lbm3_step": (ctypes.c_int, [_VP, ctypes.c_int64]),
+            "lbm3_read": (ctypes.c_int, [_VP, _D, _D, _D, _D, _D]),
+            "lbm3_mass": (ctypes.c_int, [_VP, _D]),
+            "lbm3_energy": (ctypes.c_int, [_VP, _D, _D]),
+            "lbm3_last_step_ms": (ctypes.c_double, [_VP]),
+            "lbm3_destroy": (ctypes.c_int, [_VP]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(L, name)
@@ -373,3 +403,77 @@ class Batch:
             self.close()
         except Exception:
             pass
+
+
+# ---------------------------------------------------------------- 3-D path
+def _check3(rc: int):
+    if rc != 0:
+        raise LbmError(rc, lib().lbm3_last_error().decode())
+
+
+def make_params3(p: dict, storage: str | int = "fp64") -> Lbm3Params:
+    lp = Lbm3Params()
+    lib().lbm3_default_params(ctypes.byref(lp), int(p["nx"]), int(p["ny"]), int(p["nz"]))
+    for name, _ in Lbm3Params._fields_:
+        if name in p and name != "storage":
+            setattr(lp, name, p[name])
+    lp.storage = STORAGE[storage] if isinstance(storage, str) else int(storage)
+    return lp
+
+
+class Domain3:
+    """One periodic nx x ny x nz domain (lbmgls3d.h) resident in GPU memory;
+    fields are (nz, ny, nx) arrays."""
+
+    def __init__(self, params: dict, phi, phi0, cos_theta=None, ux=None, uy=None, uz=None,
+                 storage: str = "fp64", stream=None):
+        self.params = dict(params)
+        self.storage = storage
+        self.shape = (int(params["nz"]), int(params["ny"]), int(params["nx"]))
+        self._lp = make_params3(params, storage)
+        self.nbytes = lib().lbm3_workspace_bytes(ctypes.byref(self._lp))
+        if self.nbytes == 0:
+            raise LbmError(-1, lib().lbm3_last_error().decode())
+        self._ws, ptr = alloc_workspace(self.nbytes)
+        self._stream = stream if stream is not None else current_stream_handle()
+        keep = [_arr(a, self.shape) for a in (phi, phi0, cos_theta, ux, uy, uz)]
+        h = _VP()
+        _check3(lib().lbm3_create(ctypes.byref(self._lp), _VP(ptr), self.nbytes, self._stream,
+                                  *[k[1] for k in keep], ctypes.byref(h)))
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            if DEVICE == "cuda":
+                _torch().cuda.synchronize()
+            lib().lbm3_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def step(self, n: int = 1):
+        _check3(lib().lbm3_step(self._h, int(n)))
+
+    @property
+    def last_step_ms(self) -> float:
+        return float(lib().lbm3_last_step_ms(self._h))
+
+    def read(self):
+        """phi, ux, uy, uz, P at the current level."""
+        out = [np.empty(self.shape) for _ in range(5)]
+        _check3(lib().lbm3_read(self._h, *[o.ctypes.data_as(_D) for o in out]))
+        return tuple(out)
+
+    def mass(self) -> float:
+        m = ctypes.c_double()
+        _check3(lib().lbm3_mass(self._h, ctypes.byref(m)))
+        return m.value
+
+    def energy(self):
+        ef, ek = ctypes.c_double(), ctypes.c_double()
+        _check3(lib().lbm3_energy(self._h, ctypes.byref(ef), ctypes.byref(ek)))
+        return ef.value, ek.value

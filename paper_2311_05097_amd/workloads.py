@@ -462,3 +462,67 @@ def pool_with_particles(nx: int = 1024, ny: int = 2048, n_particles: int = 64, s
     ct = np.zeros((ny, nx))
     return Workload(name or f"C5 pool + {len(parts)} particles {nx}x{ny}", p, phi, phi0, ct,
                     _zeros(nx, ny), _zeros(nx, ny), dict(seed=seed, n_particles=len(parts)), parts)
+
+
+# ------------------------------------------------------- three dimensions
+PAPER_DEFAULTS_3D = dict(
+    d0=0.4, sigma=1e-3, D=4.0, M=0.1,
+    rho1=1.0, rho2=1.0, mu1=0.1, mu2=0.1,
+    tau_phi=1.0, s0=1.0, s1=1.0, s2=1.0, s3=1.0, s4=1.0,
+    gx=0.0, gy=0.0, gz=0.0, rho_ref=0.0, fbx=0.0, fby=0.0, fbz=0.0,
+    solid_eps=1e-2,
+)
+
+
+def params3(nx: int, ny: int, nz: int, **kw) -> dict:
+    """Parameters of the three-dimensional path (the Sec. 4.1 values)."""
+    p = dict(PAPER_DEFAULTS_3D)
+    unknown = set(kw) - set(p)
+    if unknown:
+        raise KeyError(f"unknown parameters {sorted(unknown)}")
+    p.update(kw)
+    p["nx"], p["ny"], p["nz"] = int(nx), int(ny), int(nz)
+    return p
+
+
+@dataclass
+class Workload3:
+    name: str
+    params: dict
+    phi: np.ndarray       # (nz, ny, nx)
+    phi0: np.ndarray
+    cos_theta: np.ndarray
+    ux: np.ndarray
+    uy: np.ndarray
+    uz: np.ndarray
+    meta: dict = field(default_factory=dict)
+
+    def arrays(self):
+        return self.phi, self.phi0, self.cos_theta, self.ux, self.uy, self.uz
+
+
+def drop_on_slab_3d(nx: int = 64, ny: int | None = None, nz: int | None = None, slab: int = 8,
+                    R: float = 16.0, theta_deg: float = 90.0, rho_ratio: float = 10.0, mu_ratio: float = 10.0,
+                    mu1: float = 0.1, name: str | None = None, **kw) -> Workload3:
+    """A spherical drop of radius R resting on a solid slab (z < slab, tanh
+    indicator of width D), contact angle theta on the slab, periodic box;
+    rho1 = 1, rho2 = 1/rho_ratio, mu2 = mu1/mu_ratio."""
+    ny = nx if ny is None else ny
+    nz = nx if nz is None else nz
+    p = params3(nx, ny, nz, **kw)
+    p.update(rho1=1.0, rho2=1.0 / rho_ratio, mu1=mu1, mu2=mu1 / mu_ratio)
+    z, y, x = np.mgrid[0:nz, 0:ny, 0:nx].astype(np.float64)
+    phi0 = indicator(slab - 0.5 - z, p["D"])
+    r = np.sqrt((x - nx / 2.0) ** 2 + (y - ny / 2.0) ** 2 + (z - slab) ** 2)
+    phi = (1.0 - phi0) * np.tanh((R - r) / (p["D"] / 2.0))
+    zero = np.zeros_like(phi)
+    ct = np.full_like(phi, math.cos(math.radians(theta_deg)))
+    return Workload3(name or f"3-D drop on slab {nx}x{ny}x{nz}", p, phi, phi0, ct, zero, zero.copy(), zero.copy(),
+                     dict(R=R, slab=slab, theta_deg=theta_deg))
+
+
+def bench_3d() -> Workload3:
+    """The 3-D benchmark domain: 256^3 (16.8M nodes), a drop of radius 64 on a
+    slab of 16 rows, contact angle 60 degrees, density ratio 10."""
+    return drop_on_slab_3d(256, slab=16, R=64.0, theta_deg=60.0, rho_ratio=10.0, mu_ratio=10.0,
+                           mu1=0.1, name="3-D drop on slab 256^3, theta=60, rho ratio 10")

@@ -90,3 +90,55 @@ def test_binding_shares_torchs_hip_runtime():
     out = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=300)
     assert out.returncode == 0, out.stderr
     assert out.stdout.strip().splitlines()[-1] == "1"
+
+
+HEADER3 = os.path.join(ROOT, "include", "lbmgls3d.h")
+
+
+def declared_functions_3d():
+    text = re.sub(r"/\*.*?\*/", "", open(HEADER3).read(), flags=re.S)
+    return sorted(set(re.findall(r"\b(lbm3_[a-z_]+)\s*\(", text)))
+
+
+def test_library_exports_every_3d_symbol():
+    lbmgls = _lib()
+    L = ctypes.CDLL(lbmgls.LIB_PATH)
+    names = declared_functions_3d()
+    for must in ("lbm3_create", "lbm3_step", "lbm3_read", "lbm3_mass", "lbm3_energy", "lbm3_destroy"):
+        assert must in names
+    assert not [n for n in names if not hasattr(L, n)]
+    assert sorted(lbmgls.EXPORTED_3D) == names
+
+
+def test_3d_params_layout_matches_header(tmp_path):
+    lbmgls = _lib()
+    fields = [f for f, _ in lbmgls.Lbm3Params._fields_]
+    src = tmp_path / "lay3.c"
+    body = "\n".join(f'printf("{f} %zu\\n", offsetof(lbm3_params, {f}));' for f in fields)
+    src.write_text(f'#include <stdio.h>\n#include <stddef.h>\n#include "lbmgls3d.h"\n'
+                   f'int main(void){{printf("size %zu\\n", sizeof(lbm3_params));{body}return 0;}}\n')
+    exe = tmp_path / "lay3"
+    subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), "-o", str(exe), str(src)])
+    out = dict(line.split() for line in subprocess.check_output([str(exe)]).decode().splitlines())
+    assert int(out["size"]) == ctypes.sizeof(lbmgls.Lbm3Params)
+    for f in fields:
+        assert int(out[f]) == getattr(lbmgls.Lbm3Params, f).offset, f
+
+
+def test_3d_workspace_size_and_validation_host_only():
+    lbmgls = _lib()
+    L = lbmgls.lib()
+
+    def nbytes(**kw):
+        p = dict(nx=16, ny=12, nz=10)
+        p.update(kw)
+        storage = p.pop("storage", "fp64")
+        return L.lbm3_workspace_bytes(ctypes.byref(lbmgls.make_params3(p, storage)))
+
+    n64, n32 = nbytes(), nbytes(storage="fp32")
+    N = 16 * 12 * 10
+    assert n32 < n64 and n32 >= (2 * 30 * 4 + 2 * 7 * 4 + (3 + 1 + 1 + 3 + 5) * 8) * N
+    for bad in (dict(nz=2), dict(d0=0.5), dict(tau_phi=0.5), dict(storage="fp16dev"), dict(s3=2.0),
+                dict(rho2=0.0), dict(solid_eps=0.0)):
+        assert nbytes(**bad) == 0, bad
+        assert L.lbm3_last_error().decode()

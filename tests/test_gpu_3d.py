@@ -1,0 +1,134 @@
+"""Three-dimensional path on the GPU (lbmgls3d.h) against the FP64 CPU
+oracle in three dimensions (oracle/lbm3d_oracle.c), element by element.
+
+Bars (tests/parity.py): FP64 storage <= 1e-12 relative, FP32 storage <= 1e-5
+relative, on phi, u (three components) and P, in the 2-norm over the field and
+in the max-norm.  Domains are ragged (node counts not multiples of the 256-node
+block or of the 64-entry plane pitch) and periodic; the full-size 256^3 domain
+of the benchmark is checked against the oracle on a 128^3 cut of the same
+recipe and through properties that hold at any size.
+"""
+import numpy as np
+import pytest
+
+from paper_2311_05097_amd import workloads as W
+from parity import BAR, check, errors, fmt
+
+pytestmark = pytest.mark.gpu
+NAMES3 = ("phi", "ux", "uy", "uz", "P")
+
+
+@pytest.fixture(scope="module")
+def gpu():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2311_05097_amd import lbmgls
+    lbmgls.lib()
+    return lbmgls
+
+
+def _pair(gpu, w, storage, steps):
+    from oracle.oracle3d import Oracle3
+    d = gpu.Domain3(w.params, *w.arrays(), storage=storage)
+    o = Oracle3(w.params, *w.arrays())
+    m0 = d.mass()
+    d.step(steps)
+    o.step(steps)
+    errs = errors(d.read(), o.read(), NAMES3)
+    drift = abs(d.mass() - m0) / np.abs(w.phi).sum()
+    print(f"\n{w.name} {storage} {steps} steps (2-norm/max-norm): {fmt(errs)} mass_drift={drift:.2e}")
+    return d, o, errs, drift
+
+
+def _small():
+    return W.drop_on_slab_3d(20, 16, 12, slab=3, R=5.0, theta_deg=60.0, rho_ratio=10.0)
+
+
+def _ragged():
+    # 70 x 36 x 21 = 52920 nodes: 206.7 blocks of 256, pitch padding 8
+    return W.drop_on_slab_3d(70, 36, 21, slab=4, R=9.0, theta_deg=120.0, rho_ratio=10.0, mu_ratio=5.0,
+                             sigma=5e-3, gz=-2e-6, rho_ref=0.1)
+
+
+@pytest.mark.parametrize("storage", ["fp64", "fp32"])
+def test_initial_level_matches(gpu, storage):
+    w = _small()
+    from oracle.oracle3d import Oracle3
+    d = gpu.Domain3(w.params, *w.arrays(), storage=storage)
+    errs = errors(d.read(), Oracle3(w.params, *w.arrays()).read(), NAMES3)
+    print(fmt(errs))
+    check(errs, BAR[storage], ("phi",))
+    for k in ("ux", "uy", "uz", "P"):
+        assert errs[k][1] == 0.0  # at rest, P = 0 (procedure step 1)
+
+
+@pytest.mark.parametrize("storage", ["fp64", "fp32"])
+def test_small_drop_on_wetting_slab_300_steps(gpu, storage):
+    d, o, errs, drift = _pair(gpu, _small(), storage, 300)
+    check(errs, BAR[storage])
+    assert drift < (1e-13 if storage == "fp64" else 1e-9)
+    ef, ek = d.energy()
+    ef0, ek0 = o.energy()
+    assert abs(ef - ef0) <= BAR[storage] * abs(ef0) and abs(ek - ek0) <= max(BAR[storage] * 10, 1e-12) * abs(ek0)
+
+
+@pytest.mark.parametrize("storage", ["fp64", "fp32"])
+def test_ragged_domain_with_gravity_100_steps(gpu, storage):
+    _, _, errs, drift = _pair(gpu, _ragged(), storage, 100)
+    check(errs, BAR[storage])
+    assert drift < (1e-13 if storage == "fp64" else 1e-9)
+
+
+def test_runs_of_steps_compose(gpu):
+    """Stepping 7 + 13 + 1 equals stepping 21 at once, bit for bit."""
+    w = _small()
+    a = gpu.Domain3(w.params, *w.arrays(), storage="fp64")
+    b = gpu.Domain3(w.params, *w.arrays(), storage="fp64")
+    a.step(7)
+    a.step(13)
+    a.step(1)
+    b.step(21)
+    for x, y in zip(a.read(), b.read()):
+        assert np.array_equal(x, y)
+
+
+def test_benchmark_recipe_at_128_cubed_against_the_oracle(gpu):
+    """The benchmark's recipe (drop on a slab, theta 60, ratio 10) at 128^3,
+    3 steps, FP64 and FP32 storage."""
+    from oracle.oracle3d import Oracle3
+    w = W.drop_on_slab_3d(128, slab=8, R=32.0, theta_deg=60.0, rho_ratio=10.0)
+    o = Oracle3(w.params, *w.arrays())
+    o.step(3)
+    ref = o.read()
+    for storage in ("fp64", "fp32"):
+        d = gpu.Domain3(w.params, *w.arrays(), storage=storage)
+        d.step(3)
+        errs = errors(d.read(), ref, NAMES3)
+        print(f"\n128^3 {storage}: {fmt(errs)}")
+        check(errs, BAR[storage])
+        d.close()
+
+
+@pytest.mark.parametrize("storage", ["fp64", "fp32"])
+def test_full_size_properties(gpu, storage):
+    """256^3 benchmark domain, 50 steps: finite, mass conserved, and the
+    mirror symmetries of the centred drop (x -> nx - x, y -> ny - y, x <-> y)
+    kept to rounding."""
+    w = W.bench_3d()
+    d = gpu.Domain3(w.params, *w.arrays(), storage=storage)
+    m0 = d.mass()
+    d.step(50)
+    phi, ux, uy, uz, P = d.read()
+    drift = abs(d.mass() - m0) / np.abs(w.phi).sum()
+    n = w.params["nx"]
+    idx = (-np.arange(n)) % n  # x -> n - x (mod n): the reflection about x = n/2
+    sym_phi = max(np.abs(phi - phi[:, :, idx]).max(), np.abs(phi - phi[:, idx, :]).max(),
+                  np.abs(phi - np.swapaxes(phi, 1, 2)).max())
+    sym_u = max(np.abs(ux + ux[:, :, idx]).max(), np.abs(ux - np.swapaxes(uy, 1, 2)).max()) / np.abs(ux).max()
+    print(f"\n256^3 {storage}: mass drift {drift:.2e}, symmetry defect phi {sym_phi:.2e} u {sym_u:.2e}, "
+          f"|u|max {np.sqrt(ux ** 2 + uy ** 2 + uz ** 2).max():.2e}, step {d.last_step_ms:.3f} ms")
+    assert np.isfinite(phi).all() and np.isfinite(P).all()
+    assert drift < (1e-12 if storage == "fp64" else 1e-8)
+    assert sym_phi < (1e-12 if storage == "fp64" else 1e-6)
+    assert sym_u < (1e-9 if storage == "fp64" else 1e-3)
+    d.close()
