@@ -95,6 +95,57 @@ def run_gpu(workload, storage: str, steps: int, warmup: int, tile: int = 0, samp
                 kernel_ms_samples=[round(k, 5) for k in kms])
 
 
+def bytes_per_lup_3d(storage: str) -> int:
+    """Algorithmic bytes per lattice update of the 3-D path: 30 populations
+    read + 30 written, the previous level's phi, u, S (7 values) read +
+    written, phi0."""
+    r = 8 if storage == "fp64" else 4
+    return 60 * r + 14 * r + r
+
+
+def run_gpu3(workload, storage: str, steps: int, warmup: int, samples: int = 5):
+    """As run_gpu, for a 3-D domain (lbmgls3d.h): per-step kernel time is the
+    HIP-event time of each slice's step sequence (all four kernels)."""
+    import numpy as np
+    import torch
+    from paper_2311_05097_amd import lbmgls
+    d = lbmgls.Domain3(workload.params, *workload.arrays(), storage=storage)
+    m0 = d.mass()
+    d.step(warmup)
+    torch.cuda.synchronize()
+    per = max(1, steps // samples)
+    steps = per * samples
+    kms = []
+    t0 = time.perf_counter()
+    for _ in range(samples):
+        d.step(per)
+        kms.append(d.last_step_ms)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    n = workload.params["nx"] * workload.params["ny"] * workload.params["nz"]
+    finite = True
+    try:
+        d.read()
+    except lbmgls.LbmError:
+        finite = False
+    drift = abs(d.mass() - m0) / float(np.abs(workload.phi).sum()) if finite else float("nan")
+    d.close()
+    return dict(nodes=n, steps=steps, seconds=dt, ms_per_step=1e3 * dt / steps, mlups=n * steps / dt / 1e6,
+                kernel_ms=float(np.median(kms)), mass_drift=drift, finite=finite,
+                kernel_ms_samples=[round(k, 5) for k in kms])
+
+
+def roofline3(storage: str, nodes: int, kernel_ms: float, traffic=None, samples=None):
+    bpl = bytes_per_lup_3d(storage)
+    achieved = bpl * nodes / (kernel_ms * 1e-3) / 1e9
+    out = {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+           "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": traffic, "bytes_per_lup": bpl,
+           "kernel_ms": round(kernel_ms, 5)}
+    if samples:
+        out["kernel_ms_median_min_max"] = [round(kernel_ms, 5), min(samples), max(samples)]
+    return out
+
+
 def copy_ceiling(nbytes_moved: int, reps: int = 20) -> float:
     """GB/s (read + written) of torch's device-to-device copy moving the same
     number of bytes as one step (half read, half written): the bandwidth a
@@ -309,11 +360,12 @@ def main():
     ap.add_argument("--no-extra", action="store_true")
     ap.add_argument("--no-serve", action="store_true", help="skip the served-jobs leg of the default run")
     ap.add_argument("--copy-calibrate", action="store_true")
-    ap.add_argument("--workload", default="c2", choices=["c2", "r4096", "c5", "c3"],
+    ap.add_argument("--workload", default="c2", choices=["c2", "r4096", "c5", "c3", "d3"],
                     help="c2: the 1024^2 cylinder + drop case (default); r4096: the same physics "
                          "on 4096^2 (working set far above the last-level cache); c5: the 1024 x 2048 "
                          "pool with 64 free particles (step time includes the particle kernels); c3: the "
-                         "2048 x 1024 porous channel with 200 obstacles")
+                         "2048 x 1024 porous channel with 200 obstacles; d3: the 256^3 three-dimensional "
+                         "drop on a slab (fp64 or fp32 storage)")
     ap.add_argument("--walls", default="none", choices=["none", "y", "box"],
                     help="close the workload with no-flux bounce-back walls: below and above (y) or on "
                          "all four sides (box)")
@@ -346,6 +398,18 @@ def main():
 
     from paper_2311_05097_amd import workloads as W
     from paper_2311_05097_amd import autotune
+    if args.workload == "d3":
+        w3 = W.bench_3d()
+        r = run_gpu3(w3, args.storage, args.steps, args.warmup)
+        print(json.dumps({
+            "metric": "coupled-LBM MLUPS", "value": round(r["mlups"], 2), "unit": "MLUPS", "n_gpus": 1,
+            "steps": r["steps"], "warmup": args.warmup, "ms_per_step": round(r["ms_per_step"], 5),
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": DTYPE[args.storage],
+            "data": "synthetic (seeded tanh geometry, no dataset)",
+            "config": {"workload": w3.name, "nx": 256, "ny": 256, "nz": 256, "storage": args.storage},
+            "roofline": roofline3(args.storage, r["nodes"], r["kernel_ms"], samples=r["kernel_ms_samples"]),
+            "mass_drift": r["mass_drift"], "finite": r["finite"]}), flush=True)
+        return
     w = {"c2": W.config2, "r4096": W.roofline_grid, "c5": W.pool_with_particles,
          "c3": W.config3}[args.workload]()
     if args.walls != "none":
@@ -459,6 +523,15 @@ def main():
             extra[f"C5_{st}"] = {"mlups": round(e["mlups"], 1), "tile": t, "particles": int(len(C5.particles)),
                                  "ms_per_step": round(e["ms_per_step"], 5),
                                  "mass_drift": e["mass_drift"], "finite": e["finite"]}
+        # the three-dimensional path: 256^3 drop on a slab, FP32 and FP64
+        # storage (FP64 arithmetic), four kernels per step
+        w3 = W.bench_3d()
+        for st in ("fp32", "fp64"):
+            e = run_gpu3(w3, st, 200, 20)
+            extra[f"D3_256_{st}"] = {"mlups": round(e["mlups"], 1), "ms_per_step": round(e["ms_per_step"], 5),
+                                     "roofline": roofline3(st, e["nodes"], e["kernel_ms"],
+                                                           samples=e["kernel_ms_samples"]),
+                                     "mass_drift": e["mass_drift"], "finite": e["finite"]}
         # voxel solid smoothing (20 Cahn-Hilliard steps, FP64) of a 4096^2
         # binary solid: wall time of the whole call, host copies included
         from paper_2311_05097_amd import lbmgls

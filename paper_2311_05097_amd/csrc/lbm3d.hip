@@ -91,6 +91,16 @@ struct Planes3 {
     double* part;
 };
 
+// Node of this thread.  Hardware blocks are dealt round-robin to the 8 XCDs;
+// the remap gives each XCD one contiguous run of blocks (a slab of whole
+// x-rows), so the y and z neighbours a block reads were read by blocks of the
+// same XCD shortly before and sit in its L2.
+__device__ __forceinline__ int64_t node_of(int64_t nblocks) {
+    const int64_t b = blockIdx.x, q = nblocks >> 3, r = nblocks & 7;
+    const int64_t k = b & 7, j = b >> 3;
+    return (k * q + (k < r ? k : r) + j) * NT + threadIdx.x;
+}
+
 __device__ __forceinline__ double wgt(const Coef3& c, int i) { return i == 0 ? c.w[0] : (i <= 6 ? c.w[1] : c.w[2]); }
 
 // D3Q15 central-difference weights at c_s^2 = 1/3 (2/9, 1/9, 1/72).
@@ -129,7 +139,7 @@ __device__ __forceinline__ double muv_of(const Coef3& c, double ph) {
 // ---------------------------------------------------------------- statics
 // in: [0] phi0, [1] cos theta (staged FP64 inputs)
 __global__ __launch_bounds__(NT) void k3_static(Coef3 c, const double* __restrict__ in, double* __restrict__ stat) {
-    const int64_t o = (int64_t)blockIdx.x * NT + threadIdx.x;
+    const int64_t o = node_of(gridDim.x);
     if (o >= c.n) return;
     double z = in[o];
     z = z < 0.0 ? 0.0 : (z > 1.0 ? 1.0 : z);
@@ -139,7 +149,7 @@ __global__ __launch_bounds__(NT) void k3_static(Coef3 c, const double* __restric
 
 // lap psi from psi (FP64)
 __global__ __launch_bounds__(NT) void k3_lap_psi(Coef3 c, double* __restrict__ stat) {
-    const int64_t o = (int64_t)blockIdx.x * NT + threadIdx.x;
+    const int64_t o = node_of(gridDim.x);
     if (o >= c.n) return;
     Nb nb;
     neighbours(c, o, nb);
@@ -155,7 +165,7 @@ __global__ __launch_bounds__(NT) void k3_lap_psi(Coef3 c, double* __restrict__ s
 // + sum of the moving g_i.
 template <class T>
 __global__ __launch_bounds__(NT) void k3_phi(Coef3 c, Planes3<T> P, int cur) {
-    const int64_t o = (int64_t)blockIdx.x * NT + threadIdx.x;
+    const int64_t o = node_of(gridDim.x);
     if (o >= c.n) return;
     const T* g = P.pop[cur];
     double s = (double)P.hist[cur][o] + (double)g[o];
@@ -169,7 +179,7 @@ __global__ __launch_bounds__(NT) void k3_phi(Coef3 c, Planes3<T> P, int cur) {
 // - (3 D sigma/8) lap psi
 template <class T>
 __global__ __launch_bounds__(NT) void k3_mu(Coef3 c, Planes3<T> P) {
-    const int64_t o = (int64_t)blockIdx.x * NT + threadIdx.x;
+    const int64_t o = node_of(gridDim.x);
     if (o >= c.n) return;
     Nb nb;
     neighbours(c, o, nb);
@@ -186,7 +196,7 @@ __global__ __launch_bounds__(NT) void k3_mu(Coef3 c, Planes3<T> P) {
 // Consistent mass flux S = M grad(mu) (rho1 - rho2)/2.
 template <class T>
 __global__ __launch_bounds__(NT) void k3_flux(Coef3 c, Planes3<T> P) {
-    const int64_t o = (int64_t)blockIdx.x * NT + threadIdx.x;
+    const int64_t o = node_of(gridDim.x);
     if (o >= c.n) return;
     Nb nb;
     neighbours(c, o, nb);
@@ -230,7 +240,7 @@ __device__ void block_sums(double v[NPART3], double* out) {
 // level; in M3_OUT phi, u, P and the reductions.
 template <class T, int MODE>
 __global__ __launch_bounds__(NT) void k3_node(Coef3 c, Planes3<T> P, int cur) {
-    const int64_t o = (int64_t)blockIdx.x * NT + threadIdx.x;
+    const int64_t o = node_of(gridDim.x);
     const bool live = o < c.n;
     double red[NPART3] = {0.0, 0.0, 0.0, 0.0};
     if (live) {
@@ -479,7 +489,7 @@ __global__ __launch_bounds__(NT) void k3_node(Coef3 c, Planes3<T> P, int cur) {
 // f = f^eq(P = 0, rho, u, S), history = (phi, u, S); u from the staged input.
 template <class T>
 __global__ __launch_bounds__(NT) void k3_equilibrium(Coef3 c, Planes3<T> P, const double* __restrict__ uin) {
-    const int64_t o = (int64_t)blockIdx.x * NT + threadIdx.x;
+    const int64_t o = node_of(gridDim.x);
     if (o >= c.n) return;
     const int64_t pt = c.pitch;
     const double cs2 = c.cs2;
