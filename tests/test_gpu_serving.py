@@ -23,7 +23,7 @@ def test_served_jobs_equal_solo_runs(gpu, storage):
     from paper_2311_05097_amd import serve
     import torch
     spec = [(64, 60.0, 10.0, 300), (128, 120.0, 50.0, 220), (64, 90.0, 20.0, 500), (128, 45.0, 100.0, 150),
-            (192, 75.0, 30.0, 120), (64, 135.0, 150.0, 260)]
+            (192, 75.0, 30.0, 120), (64, 135.0, 80.0, 260)]
     jobs = [W.JobSpec(i, s, th, r, n, 0.0) for i, (s, th, r, n) in enumerate(spec)]
     # a budget that holds one 192^2 job and one 128^2 job: admission binds
     budget = gpu.workspace_bytes(jobs[4].workload().params, storage, 8) + \
@@ -46,9 +46,9 @@ def test_served_jobs_equal_solo_runs(gpu, storage):
 @pytest.fixture(scope="module")
 def served_vs_oracle_jobs():
     """Two small jobs of the drop-on-slab stream (128^2 at 40 and 140 degrees,
-    density ratios 30 and 200) and the oracle's phi after their step budgets."""
+    density ratios 30 and 90) and the oracle's phi after their step budgets."""
     from oracle.oracle import Oracle
-    jobs = [W.JobSpec(0, 128, 40.0, 30.0, 600, 0.0), W.JobSpec(1, 128, 140.0, 200.0, 400, 0.0)]
+    jobs = [W.JobSpec(0, 128, 40.0, 30.0, 600, 0.0), W.JobSpec(1, 128, 140.0, 90.0, 400, 0.0)]
     ref = {}
     for j in jobs:
         w = j.workload()
