@@ -68,6 +68,72 @@ __host__ __device__ inline double hrow(int k, int x, int y, int z, double cs2) {
     }
 }
 
+// Hermite moments m_k = sum_i H_k(c_i) f_i of 15 populations in the order
+// rest, +x +y +z -x -y -z, corners (bits of i - 7: x, y, z sign), through
+// the face sums and differences and a three-stage butterfly over the eight
+// corners (about 50 additions instead of the dense 15 x 15 product).
+__host__ __device__ inline void moments15(const double f[Q], double cs2, double m[Q]) {
+    const double sx = f[1] + f[4], dx = f[1] - f[4];
+    const double sy = f[2] + f[5], dy = f[2] - f[5];
+    const double sz = f[3] + f[6], dz = f[3] - f[6];
+    const double px0 = f[7] + f[8], mx0 = f[7] - f[8];      // y+, z+
+    const double px1 = f[9] + f[10], mx1 = f[9] - f[10];    // y-, z+
+    const double px2 = f[11] + f[12], mx2 = f[11] - f[12];  // y+, z-
+    const double px3 = f[13] + f[14], mx3 = f[13] - f[14];  // y-, z-
+    const double e0 = px0 + px1, ey0 = px0 - px1, e1 = px2 + px3, ey1 = px2 - px3;
+    const double o0 = mx0 + mx1, oy0 = mx0 - mx1, o1 = mx2 + mx3, oy1 = mx2 - mx3;
+    const double K = e0 + e1, Kz = e0 - e1, Ky = ey0 + ey1, Kyz = ey0 - ey1;
+    const double Kx = o0 + o1, Kxz = o0 - o1, Kxy = oy0 + oy1, Kxyz = oy0 - oy1;
+    const double m0 = f[0] + sx + sy + sz + K;
+    m[0] = m0;
+    m[1] = dx + Kx;
+    m[2] = dy + Ky;
+    m[3] = dz + Kz;
+    m[4] = sx + K - cs2 * m0;
+    m[5] = sy + K - cs2 * m0;
+    m[6] = sz + K - cs2 * m0;
+    m[7] = Kxy;
+    m[8] = Kxz;
+    m[9] = Kyz;
+    m[10] = Kx - cs2 * m[1];  // sum c_x c_y^2 f = the corners' x-odd sum
+    m[11] = Ky - cs2 * m[2];
+    m[12] = Kz - cs2 * m[3];
+    m[13] = Kxyz;
+    m[14] = K - cs2 * (sx + sy + sz + 3.0 * K) + 2.0 * cs2 * cs2 * m0;
+}
+
+// d_i = sum_k H_k(c_i) a_k (the inverse transform without the weights), by
+// the same structure run backwards.
+__host__ __device__ inline void inverse15(const double a[Q], double cs2, double d[Q]) {
+    const double tr = a[4] + a[5] + a[6];
+    d[0] = a[0] - cs2 * tr + 2.0 * cs2 * cs2 * a[14];
+    const double base = a[0] - cs2 * tr + (2.0 * cs2 * cs2 - cs2) * a[14];
+    const double Ax = base + a[4], Bx = a[1] - cs2 * a[10];
+    const double Ay = base + a[5], By = a[2] - cs2 * a[11];
+    const double Az = base + a[6], Bz = a[3] - cs2 * a[12];
+    d[1] = Ax + Bx;
+    d[4] = Ax - Bx;
+    d[2] = Ay + By;
+    d[5] = Ay - By;
+    d[3] = Az + Bz;
+    d[6] = Az - Bz;
+    const double oc = 1.0 - cs2;
+    const double E = a[0] + oc * tr + (1.0 - 3.0 * cs2 + 2.0 * cs2 * cs2) * a[14];
+    const double X = a[1] + oc * a[10], Y = a[2] + oc * a[11], Z = a[3] + oc * a[12];
+    const double Ezp = E + Z, Ezm = E - Z, Yzp = Y + a[9], Yzm = Y - a[9];
+    const double Xzp = X + a[8], Xzm = X - a[8], XYzp = a[7] + a[13], XYzm = a[7] - a[13];
+    const double pe0 = Ezp + Yzp, pe1 = Ezp - Yzp, pe2 = Ezm + Yzm, pe3 = Ezm - Yzm;
+    const double po0 = Xzp + XYzp, po1 = Xzp - XYzp, po2 = Xzm + XYzm, po3 = Xzm - XYzm;
+    d[7] = pe0 + po0;
+    d[8] = pe0 - po0;
+    d[9] = pe1 + po1;
+    d[10] = pe1 - po1;
+    d[11] = pe2 + po2;
+    d[12] = pe2 - po2;
+    d[13] = pe3 + po3;
+    d[14] = pe3 - po3;
+}
+
 struct Coef3 {
     int32_t nx, ny, nz, first;  // first: the step at level 0 (u* = the given u, P = 0)
     int64_t pitch, n;
@@ -91,36 +157,26 @@ struct Planes3 {
     double* part;
 };
 
-// Node of this thread.  Hardware blocks are dealt round-robin to the 8 XCDs;
-// the remap gives each XCD one contiguous run of blocks (a slab of whole
-// x-rows), so the y and z neighbours a block reads were read by blocks of the
-// same XCD shortly before and sit in its L2.
-__device__ __forceinline__ int64_t node_of(int64_t nblocks) {
-    const int64_t b = blockIdx.x, q = nblocks >> 3, r = nblocks & 7;
-    const int64_t k = b & 7, j = b >> 3;
-    return (k * q + (k < r ? k : r) + j) * NT + threadIdx.x;
-}
-
 __device__ __forceinline__ double wgt(const Coef3& c, int i) { return i == 0 ? c.w[0] : (i <= 6 ? c.w[1] : c.w[2]); }
 
 // D3Q15 central-difference weights at c_s^2 = 1/3 (2/9, 1/9, 1/72).
 __device__ __forceinline__ double wfd(int i) { return i == 0 ? 2.0 / 9.0 : (i <= 6 ? 1.0 / 9.0 : 1.0 / 72.0); }
 
 struct Nb {
-    int64_t o[Q];  // node index of x + c_i, periodic
+    int32_t o[Q];  // node index of x + c_i, periodic (domains hold < 2^31 nodes)
 };
 
 __device__ __forceinline__ void neighbours(const Coef3& c, int64_t o, Nb& nb) {
-    const int64_t nxy = (int64_t)c.nx * c.ny;
-    const int z = (int)(o / nxy);
-    const int64_t r = o - (int64_t)z * nxy;
-    const int y = (int)(r / c.nx), x = (int)(r - (int64_t)y * c.nx);
+    const int32_t oo = (int32_t)o, nxy = c.nx * c.ny;
+    const int z = oo / nxy;
+    const int r = oo - z * nxy;
+    const int y = r / c.nx, x = r - y * c.nx;
     const int xs[3] = {x == 0 ? c.nx - 1 : x - 1, x, x == c.nx - 1 ? 0 : x + 1};
     const int ys[3] = {y == 0 ? c.ny - 1 : y - 1, y, y == c.ny - 1 ? 0 : y + 1};
     const int zs[3] = {z == 0 ? c.nz - 1 : z - 1, z, z == c.nz - 1 ? 0 : z + 1};
 #pragma unroll
     for (int i = 0; i < Q; ++i)
-        nb.o[i] = ((int64_t)zs[czv(i) + 1] * c.ny + ys[cyv(i) + 1]) * c.nx + xs[cxv(i) + 1];
+        nb.o[i] = (zs[czv(i) + 1] * c.ny + ys[cyv(i) + 1]) * c.nx + xs[cxv(i) + 1];
 }
 
 // finite: v - v is 0 for every finite v, NaN for NaN and +-Inf
@@ -139,7 +195,7 @@ __device__ __forceinline__ double muv_of(const Coef3& c, double ph) {
 // ---------------------------------------------------------------- statics
 // in: [0] phi0, [1] cos theta (staged FP64 inputs)
 __global__ __launch_bounds__(NT) void k3_static(Coef3 c, const double* __restrict__ in, double* __restrict__ stat) {
-    const int64_t o = node_of(gridDim.x);
+    const int64_t o = (int64_t)blockIdx.x * NT + threadIdx.x;
     if (o >= c.n) return;
     double z = in[o];
     z = z < 0.0 ? 0.0 : (z > 1.0 ? 1.0 : z);
@@ -149,7 +205,7 @@ __global__ __launch_bounds__(NT) void k3_static(Coef3 c, const double* __restric
 
 // lap psi from psi (FP64)
 __global__ __launch_bounds__(NT) void k3_lap_psi(Coef3 c, double* __restrict__ stat) {
-    const int64_t o = node_of(gridDim.x);
+    const int64_t o = (int64_t)blockIdx.x * NT + threadIdx.x;
     if (o >= c.n) return;
     Nb nb;
     neighbours(c, o, nb);
@@ -165,7 +221,7 @@ __global__ __launch_bounds__(NT) void k3_lap_psi(Coef3 c, double* __restrict__ s
 // + sum of the moving g_i.
 template <class T>
 __global__ __launch_bounds__(NT) void k3_phi(Coef3 c, Planes3<T> P, int cur) {
-    const int64_t o = node_of(gridDim.x);
+    const int64_t o = (int64_t)blockIdx.x * NT + threadIdx.x;
     if (o >= c.n) return;
     const T* g = P.pop[cur];
     double s = (double)P.hist[cur][o] + (double)g[o];
@@ -179,7 +235,7 @@ __global__ __launch_bounds__(NT) void k3_phi(Coef3 c, Planes3<T> P, int cur) {
 // - (3 D sigma/8) lap psi
 template <class T>
 __global__ __launch_bounds__(NT) void k3_mu(Coef3 c, Planes3<T> P) {
-    const int64_t o = node_of(gridDim.x);
+    const int64_t o = (int64_t)blockIdx.x * NT + threadIdx.x;
     if (o >= c.n) return;
     Nb nb;
     neighbours(c, o, nb);
@@ -196,7 +252,7 @@ __global__ __launch_bounds__(NT) void k3_mu(Coef3 c, Planes3<T> P) {
 // Consistent mass flux S = M grad(mu) (rho1 - rho2)/2.
 template <class T>
 __global__ __launch_bounds__(NT) void k3_flux(Coef3 c, Planes3<T> P) {
-    const int64_t o = node_of(gridDim.x);
+    const int64_t o = (int64_t)blockIdx.x * NT + threadIdx.x;
     if (o >= c.n) return;
     Nb nb;
     neighbours(c, o, nb);
@@ -240,7 +296,7 @@ __device__ void block_sums(double v[NPART3], double* out) {
 // level; in M3_OUT phi, u, P and the reductions.
 template <class T, int MODE>
 __global__ __launch_bounds__(NT) void k3_node(Coef3 c, Planes3<T> P, int cur) {
-    const int64_t o = node_of(gridDim.x);
+    const int64_t o = (int64_t)blockIdx.x * NT + threadIdx.x;
     const bool live = o < c.n;
     double red[NPART3] = {0.0, 0.0, 0.0, 0.0};
     if (live) {
@@ -379,13 +435,7 @@ __global__ __launch_bounds__(NT) void k3_node(Coef3 c, Planes3<T> P, int cur) {
                         (a == b ? (1.0 - 3.0 * cs2) * udr : 0.0);
             }
             double m[Q];
-#pragma unroll
-            for (int k = 0; k < Q; ++k) {
-                double s = 0.0;
-#pragma unroll
-                for (int i = 0; i < Q; ++i) s += hrow(k, cxv(i), cyv(i), czv(i), cs2) * f[i];
-                m[k] = s;
-            }
+            moments15(f, cs2, m);
             double meq[Q], src[Q], rate[Q];
             const double r2 = rho * 1.0;
             meq[0] = 0.0;
@@ -419,26 +469,17 @@ __global__ __launch_bounds__(NT) void k3_node(Coef3 c, Planes3<T> P, int cur) {
             double dm[Q];
 #pragma unroll
             for (int k = 0; k < Q; ++k) dm[k] = (-rate[k] * (m[k] - meq[k]) + (1.0 - 0.5 * rate[k]) * src[k]) * c.inv_norm[k];
+            double df[Q];
+            inverse15(dm, cs2, df);
 #pragma unroll
-            for (int i = 0; i < Q; ++i) {
-                double s = 0.0;
-#pragma unroll
-                for (int k = 0; k < Q; ++k) s += hrow(k, cxv(i), cyv(i), czv(i), cs2) * dm[k];
-                fn[(int64_t)i * pt + nb.o[i]] = (T)(f[i] + wgt(c, i) * s);
-            }
+            for (int i = 0; i < Q; ++i) fn[(int64_t)i * pt + nb.o[i]] = (T)(f[i] + wgt(c, i) * df[i]);
             // ---- phase-field collision (Sec. 3.1)
             double g[Q];
             g[0] = php + (double)gp[o];
 #pragma unroll
             for (int i = 1; i < Q; ++i) g[i] = (double)gp[(int64_t)i * pt + o];
             double mg[Q];
-#pragma unroll
-            for (int k = 0; k < Q; ++k) {
-                double s = 0.0;
-#pragma unroll
-                for (int i = 0; i < Q; ++i) s += hrow(k, cxv(i), cyv(i), czv(i), cs2) * g[i];
-                mg[k] = s;
-            }
+            moments15(g, cs2, mg);
             const double em = c.eta * mu;
             double geq[Q], gsrc[Q];
             geq[0] = ph;
@@ -461,12 +502,11 @@ __global__ __launch_bounds__(NT) void k3_node(Coef3 c, Planes3<T> P, int cur) {
             for (int k = 0; k < Q; ++k)
                 dm[k] = (-c.sg[k] * (mg[k] - geq[k]) + (1.0 - 0.5 * c.sg[k]) * gsrc[k]) * c.inv_norm[k];
             const T phs = (T)ph;  // the history value g_0 is stored against
+            double dg[Q];
+            inverse15(dm, cs2, dg);
 #pragma unroll
             for (int i = 0; i < Q; ++i) {
-                double s = 0.0;
-#pragma unroll
-                for (int k = 0; k < Q; ++k) s += hrow(k, cxv(i), cyv(i), czv(i), cs2) * dm[k];
-                const double gi = g[i] + wgt(c, i) * s;
+                const double gi = g[i] + wgt(c, i) * dg[i];
                 if (i == 0)
                     gn[o] = (T)(gi - (double)phs);
                 else
@@ -489,7 +529,7 @@ __global__ __launch_bounds__(NT) void k3_node(Coef3 c, Planes3<T> P, int cur) {
 // f = f^eq(P = 0, rho, u, S), history = (phi, u, S); u from the staged input.
 template <class T>
 __global__ __launch_bounds__(NT) void k3_equilibrium(Coef3 c, Planes3<T> P, const double* __restrict__ uin) {
-    const int64_t o = node_of(gridDim.x);
+    const int64_t o = (int64_t)blockIdx.x * NT + threadIdx.x;
     if (o >= c.n) return;
     const int64_t pt = c.pitch;
     const double cs2 = c.cs2;
