@@ -8,8 +8,13 @@
 // tensor built from S).  In 3-D a 64 x 4 x 4 block would have to rebuild the
 // order parameter from 15 populations at ~7x as many ring nodes as it owns.
 // Instead the order parameter, mu and S are written once per step as FP64
-// planes (8 + 8 + 24 bytes per node) and read with their halos through the
-// caches.
+// planes (8 + 8 + 24 bytes per node); mu and S read their one-node rings
+// through the caches, and the node update (k3_march) marches along z over a
+// 64 x 4 column, holding three slices of phi, S and the lagged velocity with
+// their ring in LDS, so that each of those values is read from memory about
+// 1.3 times per step instead of once per neighbour that needs it.
+//
+// Arithmetic is FP64 for either storage; FP32 storage rounds what is stored.
 //
 // Layout (one domain, N = nx ny nz nodes, x fastest, planes of `pitch`
 // entries, pitch = N rounded up to 64):
@@ -72,19 +77,20 @@ __host__ __device__ inline double hrow(int k, int x, int y, int z, double cs2) {
 // rest, +x +y +z -x -y -z, corners (bits of i - 7: x, y, z sign), through
 // the face sums and differences and a three-stage butterfly over the eight
 // corners (about 50 additions instead of the dense 15 x 15 product).
-__host__ __device__ inline void moments15(const double f[Q], double cs2, double m[Q]) {
-    const double sx = f[1] + f[4], dx = f[1] - f[4];
-    const double sy = f[2] + f[5], dy = f[2] - f[5];
-    const double sz = f[3] + f[6], dz = f[3] - f[6];
-    const double px0 = f[7] + f[8], mx0 = f[7] - f[8];      // y+, z+
-    const double px1 = f[9] + f[10], mx1 = f[9] - f[10];    // y-, z+
-    const double px2 = f[11] + f[12], mx2 = f[11] - f[12];  // y+, z-
-    const double px3 = f[13] + f[14], mx3 = f[13] - f[14];  // y-, z-
-    const double e0 = px0 + px1, ey0 = px0 - px1, e1 = px2 + px3, ey1 = px2 - px3;
-    const double o0 = mx0 + mx1, oy0 = mx0 - mx1, o1 = mx2 + mx3, oy1 = mx2 - mx3;
-    const double K = e0 + e1, Kz = e0 - e1, Ky = ey0 + ey1, Kyz = ey0 - ey1;
-    const double Kx = o0 + o1, Kxz = o0 - o1, Kxy = oy0 + oy1, Kxyz = oy0 - oy1;
-    const double m0 = f[0] + sx + sy + sz + K;
+template <class R>
+__host__ __device__ inline void moments15(const R f[Q], R cs2, R m[Q]) {
+    const R sx = f[1] + f[4], dx = f[1] - f[4];
+    const R sy = f[2] + f[5], dy = f[2] - f[5];
+    const R sz = f[3] + f[6], dz = f[3] - f[6];
+    const R px0 = f[7] + f[8], mx0 = f[7] - f[8];      // y+, z+
+    const R px1 = f[9] + f[10], mx1 = f[9] - f[10];    // y-, z+
+    const R px2 = f[11] + f[12], mx2 = f[11] - f[12];  // y+, z-
+    const R px3 = f[13] + f[14], mx3 = f[13] - f[14];  // y-, z-
+    const R e0 = px0 + px1, ey0 = px0 - px1, e1 = px2 + px3, ey1 = px2 - px3;
+    const R o0 = mx0 + mx1, oy0 = mx0 - mx1, o1 = mx2 + mx3, oy1 = mx2 - mx3;
+    const R K = e0 + e1, Kz = e0 - e1, Ky = ey0 + ey1, Kyz = ey0 - ey1;
+    const R Kx = o0 + o1, Kxz = o0 - o1, Kxy = oy0 + oy1, Kxyz = oy0 - oy1;
+    const R m0 = f[0] + sx + sy + sz + K;
     m[0] = m0;
     m[1] = dx + Kx;
     m[2] = dy + Ky;
@@ -99,31 +105,32 @@ __host__ __device__ inline void moments15(const double f[Q], double cs2, double 
     m[11] = Ky - cs2 * m[2];
     m[12] = Kz - cs2 * m[3];
     m[13] = Kxyz;
-    m[14] = K - cs2 * (sx + sy + sz + 3.0 * K) + 2.0 * cs2 * cs2 * m0;
+    m[14] = K - cs2 * (sx + sy + sz + R(3) * K) + R(2) * cs2 * cs2 * m0;
 }
 
 // d_i = sum_k H_k(c_i) a_k (the inverse transform without the weights), by
 // the same structure run backwards.
-__host__ __device__ inline void inverse15(const double a[Q], double cs2, double d[Q]) {
-    const double tr = a[4] + a[5] + a[6];
-    d[0] = a[0] - cs2 * tr + 2.0 * cs2 * cs2 * a[14];
-    const double base = a[0] - cs2 * tr + (2.0 * cs2 * cs2 - cs2) * a[14];
-    const double Ax = base + a[4], Bx = a[1] - cs2 * a[10];
-    const double Ay = base + a[5], By = a[2] - cs2 * a[11];
-    const double Az = base + a[6], Bz = a[3] - cs2 * a[12];
+template <class R>
+__host__ __device__ inline void inverse15(const R a[Q], R cs2, R d[Q]) {
+    const R tr = a[4] + a[5] + a[6];
+    d[0] = a[0] - cs2 * tr + R(2) * cs2 * cs2 * a[14];
+    const R base = a[0] - cs2 * tr + (R(2) * cs2 * cs2 - cs2) * a[14];
+    const R Ax = base + a[4], Bx = a[1] - cs2 * a[10];
+    const R Ay = base + a[5], By = a[2] - cs2 * a[11];
+    const R Az = base + a[6], Bz = a[3] - cs2 * a[12];
     d[1] = Ax + Bx;
     d[4] = Ax - Bx;
     d[2] = Ay + By;
     d[5] = Ay - By;
     d[3] = Az + Bz;
     d[6] = Az - Bz;
-    const double oc = 1.0 - cs2;
-    const double E = a[0] + oc * tr + (1.0 - 3.0 * cs2 + 2.0 * cs2 * cs2) * a[14];
-    const double X = a[1] + oc * a[10], Y = a[2] + oc * a[11], Z = a[3] + oc * a[12];
-    const double Ezp = E + Z, Ezm = E - Z, Yzp = Y + a[9], Yzm = Y - a[9];
-    const double Xzp = X + a[8], Xzm = X - a[8], XYzp = a[7] + a[13], XYzm = a[7] - a[13];
-    const double pe0 = Ezp + Yzp, pe1 = Ezp - Yzp, pe2 = Ezm + Yzm, pe3 = Ezm - Yzm;
-    const double po0 = Xzp + XYzp, po1 = Xzp - XYzp, po2 = Xzm + XYzm, po3 = Xzm - XYzm;
+    const R oc = R(1) - cs2;
+    const R E = a[0] + oc * tr + (R(1) - R(3) * cs2 + R(2) * cs2 * cs2) * a[14];
+    const R X = a[1] + oc * a[10], Y = a[2] + oc * a[11], Z = a[3] + oc * a[12];
+    const R Ezp = E + Z, Ezm = E - Z, Yzp = Y + a[9], Yzm = Y - a[9];
+    const R Xzp = X + a[8], Xzm = X - a[8], XYzp = a[7] + a[13], XYzm = a[7] - a[13];
+    const R pe0 = Ezp + Yzp, pe1 = Ezp - Yzp, pe2 = Ezm + Yzm, pe3 = Ezm - Yzm;
+    const R po0 = Xzp + XYzp, po1 = Xzp - XYzp, po2 = Xzm + XYzm, po3 = Xzm - XYzm;
     d[7] = pe0 + po0;
     d[8] = pe0 - po0;
     d[9] = pe1 + po1;
@@ -140,10 +147,17 @@ struct Coef3 {
     double cs2, w[3], K, eta;   // weights: rest, face, corner
     double sigma, Dw, Mob, rho1, rho2, mu1, mu2;
     double gx, gy, gz, rho_ref, fbx, fby, fbz, solid_eps;
-    double sg[Q];               // phase-field rates
     double s1, s3;              // flow rates of the first and third moments
-    double inv_norm[Q];         // 1 / sum_i w_i H_k(c_i)^2
+    double inv_norm[7];         // 1 / sum_i w_i H_k(c_i)^2 by row class (hcls)
+    double gA[7];               // phase field: -s_k / |H_k|^2 by row class
+    double gB1;                 // phase field: (1 - s_k/2) / |H_k|^2 of the first moments
 };
+
+// The Hermite rows fall into seven classes of equal norm and equal
+// phase-field rate: 0 | 1-3 | 4-6 | 7-9 | 10-12 | 13 | 14.
+__host__ __device__ constexpr int hcls(int k) {
+    return k == 0 ? 0 : (k <= 3 ? 1 : (k <= 6 ? 2 : (k <= 9 ? 3 : (k <= 12 ? 4 : (k == 13 ? 5 : 6)))));
+}
 
 template <class T>
 struct Planes3 {
@@ -166,17 +180,21 @@ struct Nb {
     int32_t o[Q];  // node index of x + c_i, periodic (domains hold < 2^31 nodes)
 };
 
-__device__ __forceinline__ void neighbours(const Coef3& c, int64_t o, Nb& nb) {
-    const int32_t oo = (int32_t)o, nxy = c.nx * c.ny;
-    const int z = oo / nxy;
-    const int r = oo - z * nxy;
-    const int y = r / c.nx, x = r - y * c.nx;
+__device__ __forceinline__ void neighbours_xyz(const Coef3& c, int x, int y, int z, Nb& nb) {
     const int xs[3] = {x == 0 ? c.nx - 1 : x - 1, x, x == c.nx - 1 ? 0 : x + 1};
     const int ys[3] = {y == 0 ? c.ny - 1 : y - 1, y, y == c.ny - 1 ? 0 : y + 1};
     const int zs[3] = {z == 0 ? c.nz - 1 : z - 1, z, z == c.nz - 1 ? 0 : z + 1};
 #pragma unroll
     for (int i = 0; i < Q; ++i)
         nb.o[i] = (zs[czv(i) + 1] * c.ny + ys[cyv(i) + 1]) * c.nx + xs[cxv(i) + 1];
+}
+
+__device__ __forceinline__ void neighbours(const Coef3& c, int64_t o, Nb& nb) {
+    const int32_t oo = (int32_t)o, nxy = c.nx * c.ny;
+    const int z = oo / nxy;
+    const int r = oo - z * nxy;
+    const int y = r / c.nx, x = r - y * c.nx;
+    neighbours_xyz(c, x, y, z, nb);
 }
 
 // finite: v - v is 0 for every finite v, NaN for NaN and +-Inf
@@ -290,239 +308,358 @@ __device__ void block_sums(double v[NPART3], double* out) {
         for (int k = 0; k < NPART3; ++k) out[(int64_t)blockIdx.x * NPART3 + k] = red[k][0];
 }
 
+// sum_i c_i v_i over the nonzero components of a lattice velocity (the
+// unrolled loops fold it to additions and negations: -0 + v is v exactly)
+template <class R>
+__device__ __forceinline__ R cdot(int cx, int cy, int cz, const R v[3]) {
+    R s = R(-0.0);
+    if (cx) s = cx > 0 ? s + v[0] : s - v[0];
+    if (cy) s = cy > 0 ? s + v[1] : s - v[1];
+    if (cz) s = cz > 0 ? s + v[2] : s - v[2];
+    return s;
+}
+
+
+// Neighbour values of the current level at x + c_i (i = 0: the node
+// itself): the order parameter, the mass flux S and the lagged velocity,
+// from the planes (NbPlanes) or from the slices a marching block holds in LDS
+// (NbLds).
+template <class T>
+struct NbPlanes {
+    const double* phi;
+    const double* S;
+    const T* u;  // history plane of u_x; u_y and u_z follow at pitch strides
+    int64_t pt;
+    __device__ __forceinline__ double ph(int i, const Nb& nb) const { return phi[nb.o[i]]; }
+    __device__ __forceinline__ double s(int i, int k, const Nb& nb) const { return (double)S[k * pt + nb.o[i]]; }
+    __device__ __forceinline__ T v(int i, int k, const Nb& nb) const { return u[k * pt + nb.o[i]]; }
+};
+
+constexpr int MX = 64, MY = NT / MX, MZ = 8;  // marching column and slices per block
+constexpr int MW = MX + 2, MP = MW * (MY + 2);  // LDS slice with the one-node ring
+
+template <class T>
+struct NbLds {
+    const double* phi[3];  // slices z - 1, z, z + 1
+    const double* S[3];     // [3][MP] each
+    const T* u[3];
+    int q;                 // the node's index in its slice
+    __device__ __forceinline__ int at(int i) const { return q + cyv(i) * MW + cxv(i); }
+    __device__ __forceinline__ double ph(int i, const Nb&) const { return phi[czv(i) + 1][at(i)]; }
+    __device__ __forceinline__ double s(int i, int k, const Nb&) const { return S[czv(i) + 1][k * MP + at(i)]; }
+    __device__ __forceinline__ T v(int i, int k, const Nb&) const { return u[czv(i) + 1][k * MP + at(i)]; }
+};
+
 // Node update of the current level (steps 4-6 and 2 of the procedure):
 // grad phi, grad rho, F_c, F, u*, the solid force, u, P, then in M3_STEP
 // both collisions, the push into the other copy and the history of this
 // level; in M3_OUT phi, u, P and the reductions.
+// The phase-field collision acts on g with g_0 taken relative to the
+// history order parameter (g_0 - phi_hist, as it is stored): the moments of
+// g then differ from those of the full g by phi_hist times the Hermite rows
+// at the rest velocity, which the equilibria below subtract as well.
+template <class T, int MODE, class NbA>
+__device__ __forceinline__ void node_body(const Coef3& c, const Planes3<T>& P, int cur, int64_t o,
+                                          const Nb& nb, const NbA& A, double red[NPART3]) {
+    using R = double;  // FP64 arithmetic for either storage
+    const int64_t pt = c.pitch;
+    const T* H = P.hist[cur];
+    const R cs2 = c.cs2;
+    // ---- gradients of phi and rho (FP64), F_c = div(S u_lag - u_lag S)/2
+    const double phd = A.ph(0, nb);
+    double dpd[3] = {0.0, 0.0, 0.0}, drd[3] = {0.0, 0.0, 0.0};
+    R fc[3] = {R(0), R(0), R(0)};
+#pragma unroll
+    for (int i = 1; i < Q; ++i) {
+        const double wi = wfd(i);
+        const double pn = A.ph(i, nb), rn = rho_of(c, pn);
+        const int ci[3] = {cxv(i), cyv(i), czv(i)};
+        const R Sn[3] = {A.s(i, 0, nb), A.s(i, 1, nb), A.s(i, 2, nb)};
+        const R un[3] = {A.v(i, 0, nb), A.v(i, 1, nb), A.v(i, 2, nb)};
+        const R cS = cdot(ci[0], ci[1], ci[2], Sn);
+        const R cu = cdot(ci[0], ci[1], ci[2], un);
+#pragma unroll
+        for (int b = 0; b < 3; ++b) {
+            if (ci[b]) {
+                dpd[b] += (ci[b] > 0 ? wi : -wi) * pn;
+                drd[b] += (ci[b] > 0 ? wi : -wi) * rn;
+            }
+            fc[b] += R(wi) * (cS * un[b] - cu * Sn[b]);
+        }
+    }
+    R dp[3], dr[3];
+#pragma unroll
+    for (int b = 0; b < 3; ++b) {
+        dpd[b] *= 3.0;
+        dp[b] = (R)dpd[b];
+        dr[b] = (R)(3.0 * drd[b]);
+        fc[b] *= R(1.5);  // 3 (1/c_s^2) x 1/2
+    }
+    const R ph = (R)phd;
+    const R rho = rho_of(c, ph);
+    const R mu = (R)P.mu[o];
+    const R S[3] = {A.s(0, 0, nb), A.s(0, 1, nb), A.s(0, 2, nb)};
+    const R z = (R)P.stat[o];
+    const R F[3] = {mu * dp[0] + (rho - c.rho_ref) * c.gx + (R(1) - z) * c.fbx + fc[0],
+                    mu * dp[1] + (rho - c.rho_ref) * c.gy + (R(1) - z) * c.fby + fc[1],
+                    mu * dp[2] + (rho - c.rho_ref) * c.gz + (R(1) - z) * c.fbz + fc[2]};
+    // ---- history of the previous level
+    const T php = H[o];
+    const R up[3] = {A.v(0, 0, nb), A.v(0, 1, nb), A.v(0, 2, nb)};
+    const R Sp[3] = {H[4 * pt + o], H[5 * pt + o], H[6 * pt + o]};
+    // ---- flow populations and their Hermite moments
+    const T* gp = P.pop[cur];
+    const T* fp = gp + (int64_t)Q * pt;
+    R f[Q];
+#pragma unroll
+    for (int i = 0; i < Q; ++i) f[i] = fp[(int64_t)i * pt + o];
+    // ---- viscosity: nu = (1/s2a - 1/2)(1 - c_s^2)/2 = (1/s2b - 1/2) c_s^2
+    R om = R(1) - z;
+    om = om < c.solid_eps ? c.solid_eps : om;
+    const R nu = muv_of(c, ph) / (rho * om);
+    const R ta = nu / ((R(1) - cs2) * R(0.5)) + R(0.5), tb = nu / cs2 + R(0.5);
+    const R s2a = R(1) / ta, s2b = R(1) / tb;
+    // ---- u*, solid force, u, P (Eqs. uStar, u)
+    R us[3], af[3], u[3];
+    if (c.first) {
+#pragma unroll
+        for (int b = 0; b < 3; ++b) us[b] = up[b];
+    } else {
+        const R j[3] = {(f[1] - f[4]) + (((f[7] - f[8]) + (f[9] - f[10])) + ((f[11] - f[12]) + (f[13] - f[14]))),
+            (f[2] - f[5]) + (((f[7] + f[8]) - (f[9] + f[10])) + ((f[11] + f[12]) - (f[13] + f[14]))),
+            (f[3] - f[6]) + (((f[7] + f[8]) + (f[9] + f[10])) - ((f[11] + f[12]) + (f[13] + f[14])))};
+#pragma unroll
+        for (int b = 0; b < 3; ++b) us[b] = (j[b] + R(0.5) * F[b]) / rho;
+    }
+#pragma unroll
+    for (int b = 0; b < 3; ++b) {
+        af[b] = -z * us[b];  // phi0 (u_s - u*) with u_s = 0
+        u[b] = c.first ? us[b] : us[b] + R(0.5) * af[b];
+    }
+    const R udr = u[0] * dr[0] + u[1] * dr[1] + u[2] * dr[2];
+    const R Su = S[0] * u[0] + S[1] * u[1] + S[2] * u[2];
+    const R q = rho * (u[0] * u[0] + u[1] * u[1] + u[2] * u[2]) - Su;
+    const R rhop = rho_of(c, (R)php);
+    const R qp = rhop * (up[0] * up[0] + up[1] * up[1] + up[2] * up[2]) -
+                 (Sp[0] * up[0] + Sp[1] * up[1] + Sp[2] * up[2]);
+    R Pr = R(0);
+    if (!c.first) {
+        R sum = f[1];
+#pragma unroll
+        for (int i = 2; i < Q; ++i) sum += f[i];
+        // H = -2 K (1 - 3 d0)(1/s2a - 1/2) (the printed 3-D factor with s0 = s2a)
+        const R Hf = R(-2) * c.K * (R(1) - R(3) * cs2) * (ta - R(0.5));
+        Pr = cs2 / (R(1) - c.w[0]) * (sum + (R(0.5) + Hf) * udr - c.w[0] * q / (R(1) - cs2) + R(0.5) * c.K * (q - qp));
+    }
+    if (MODE == M3_OUT) {
+        double* out = P.out;
+        const double ud[3] = {(double)u[0], (double)u[1], (double)u[2]};
+        out[o] = phd;
+        out[pt + o] = ud[0];
+        out[2 * pt + o] = ud[1];
+        out[3 * pt + o] = ud[2];
+        out[4 * pt + o] = (double)Pr;
+        // Eq. (2energy) with psi; grad psi from the static plane
+        const double* psi = P.stat + pt;
+        double gq[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+        for (int i = 1; i < Q; ++i) {
+            const double v = wfd(i) * psi[nb.o[i]];
+            gq[0] += cxv(i) * v;
+            gq[1] += cyv(i) * v;
+            gq[2] += czv(i) * v;
+        }
+        const double zd = P.stat[o], qq = psi[o], s = c.sigma, D = c.Dw;
+        const double g2 = dpd[0] * dpd[0] + dpd[1] * dpd[1] + dpd[2] * dpd[2];
+        const double gpq = 3.0 * (gq[0] * dpd[0] + gq[1] * dpd[1] + gq[2] * dpd[2]);
+        red[0] = phd;
+        red[1] = 3.0 * s / (4.0 * D) * (1.0 - phd) * (1.0 - phd) * (1.0 + phd) * (1.0 + phd) + 3.0 * D * s / 16.0 * g2 +
+                 9.0 * s / (2.0 * D) * zd * zd * phd * phd + 3.0 * s / D * qq * phd * (phd * phd + zd * zd - 1.0) +
+                 3.0 * D * s / 8.0 * gpq;
+        red[2] = 0.5 * (double)rho * (ud[0] * ud[0] + ud[1] * ud[1] + ud[2] * ud[2]);
+        red[3] = (fin(phd) && fin(ud[0]) && fin(ud[1]) && fin(ud[2]) && fin((double)Pr)) ? 0.0 : 1.0;
+    } else {
+        const int nxt = cur ^ 1;
+        T* gn = P.pop[nxt];
+        T* fn = gn + (int64_t)Q * pt;
+        // ---- flow collision in Hermite moments: dm_k = -s_k (m_k - m_k^eq) + (1 - s_k/2) F_k,
+        // f* = f + w_i sum_k H_k(c_i) dm_k / |H_k|^2
+        const int A6[6] = {0, 1, 2, 0, 0, 1}, B6[6] = {0, 1, 2, 1, 2, 2};
+        R M2[6];
+#pragma unroll
+        for (int k = 0; k < 6; ++k) {
+            const int ka = A6[k], kb = B6[k];
+            const R T_now = R(0.5) * (S[ka] * u[kb] + u[ka] * S[kb]);
+            const R T_old = R(0.5) * (Sp[ka] * up[kb] + up[ka] * Sp[kb]);
+            M2[k] = (u[ka] * F[kb] + F[ka] * u[kb]) - (T_now - T_old) + cs2 * (u[ka] * dr[kb] + dr[ka] * u[kb]) +
+                    (ka == kb ? (R(1) - R(3) * cs2) * udr : R(0));
+        }
+        R m[Q];
+        moments15(f, cs2, m);
+        R meq[Q], src[Q], rate[Q];
+        meq[0] = R(0);
+        src[0] = udr;
+        rate[0] = s2a;
+#pragma unroll
+        for (int b = 0; b < 3; ++b) {
+            meq[1 + b] = rho * u[b];
+            src[1 + b] = F[b] + rho * af[b];
+            rate[1 + b] = c.s1;
+            meq[4 + b] = Pr + rho * u[b] * u[b] - S[b] * u[b];
+            src[4 + b] = M2[b];
+            rate[4 + b] = s2a;
+        }
+        meq[7] = rho * u[0] * u[1] - R(0.5) * (S[0] * u[1] + u[0] * S[1]);
+        meq[8] = rho * u[0] * u[2] - R(0.5) * (S[0] * u[2] + u[0] * S[2]);
+        meq[9] = rho * u[1] * u[2] - R(0.5) * (S[1] * u[2] + u[1] * S[2]);
+        src[7] = M2[3];
+        src[8] = M2[4];
+        src[9] = M2[5];
+        rate[7] = rate[8] = rate[9] = s2b;
+#pragma unroll
+        for (int k = 10; k < 14; ++k) {
+            meq[k] = R(0);
+            src[k] = R(0);
+            rate[k] = c.s3;
+        }
+        meq[14] = R(-2) * cs2 * Pr;
+        src[14] = R(0);
+        rate[14] = s2a;
+        R dm[Q];
+#pragma unroll
+        for (int k = 0; k < Q; ++k)
+            dm[k] = (-rate[k] * (m[k] - meq[k]) + (R(1) - R(0.5) * rate[k]) * src[k]) * c.inv_norm[hcls(k)];
+        R df[Q];
+        inverse15(dm, cs2, df);
+#pragma unroll
+        for (int i = 0; i < Q; ++i) fn[(int64_t)i * pt + nb.o[i]] = f[i] + wgt(c, i) * df[i];
+        // ---- phase-field collision (Sec. 3.1), g_0 relative to phi_hist
+        R g[Q];
+#pragma unroll
+        for (int i = 0; i < Q; ++i) g[i] = gp[(int64_t)i * pt + o];
+        R mg[Q];
+        moments15(g, cs2, mg);
+        const R em = c.eta * mu;
+        const R dph = (R)(phd - (double)php);  // phi - phi_hist
+        R geq[Q], gsrc[Q];
+        geq[0] = dph;
+        gsrc[0] = R(0);
+#pragma unroll
+        for (int b = 0; b < 3; ++b) {
+            geq[1 + b] = ph * u[b];
+            gsrc[1 + b] = ph * u[b] - php * up[b];  // d_t(phi u), backward difference
+            geq[4 + b] = -cs2 * (dph - em);
+            gsrc[4 + b] = R(0);
+        }
+#pragma unroll
+        for (int k = 7; k < 14; ++k) {
+            geq[k] = R(0);
+            gsrc[k] = R(0);
+        }
+        geq[14] = R(2) * cs2 * cs2 * (dph - em);
+        gsrc[14] = R(0);
+#pragma unroll
+        for (int k = 0; k < Q; ++k)
+            dm[k] = c.gA[hcls(k)] * (mg[k] - geq[k]) + (hcls(k) == 1 ? c.gB1 * gsrc[k] : R(0));
+        const T phs = (T)phd;  // the history value g_0 is stored against
+        R dg[Q];
+        inverse15(dm, cs2, dg);
+        gn[o] = g[0] + wgt(c, 0) * dg[0] + (R)((double)php - (double)phs);
+#pragma unroll
+        for (int i = 1; i < Q; ++i) gn[(int64_t)i * pt + nb.o[i]] = g[i] + wgt(c, i) * dg[i];
+        // ---- history of this level
+        T* Hn = P.hist[nxt];
+        Hn[o] = phs;
+#pragma unroll
+        for (int b = 0; b < 3; ++b) {
+            Hn[(1 + b) * pt + o] = u[b];
+            Hn[(4 + b) * pt + o] = S[b];
+        }
+    }
+}
+
 template <class T, int MODE>
 __global__ __launch_bounds__(NT) void k3_node(Coef3 c, Planes3<T> P, int cur) {
     const int64_t o = (int64_t)blockIdx.x * NT + threadIdx.x;
-    const bool live = o < c.n;
     double red[NPART3] = {0.0, 0.0, 0.0, 0.0};
-    if (live) {
+    if (o < c.n) {
         Nb nb;
         neighbours(c, o, nb);
-        const int64_t pt = c.pitch;
-        const T* H = P.hist[cur];
-        const double cs2 = c.cs2;
-        // ---- gradients of phi and rho, F_c = div(S u_lag - u_lag S)/2
-        const double ph = P.phi[o];
-        const double rho = rho_of(c, ph);
-        double dp[3] = {0.0, 0.0, 0.0}, dr[3] = {0.0, 0.0, 0.0}, fc[3] = {0.0, 0.0, 0.0};
-#pragma unroll
-        for (int i = 1; i < Q; ++i) {
-            const int64_t n = nb.o[i];
-            const double wi = wfd(i);
-            const double pn = P.phi[n], rn = rho_of(c, pn);
-            const double ci[3] = {(double)cxv(i), (double)cyv(i), (double)czv(i)};
-            const double Sn[3] = {P.S[n], P.S[pt + n], P.S[2 * pt + n]};
-            const double un[3] = {(double)H[pt + n], (double)H[2 * pt + n], (double)H[3 * pt + n]};
-            const double cS = ci[0] * Sn[0] + ci[1] * Sn[1] + ci[2] * Sn[2];
-            const double cu = ci[0] * un[0] + ci[1] * un[1] + ci[2] * un[2];
-#pragma unroll
-            for (int a = 0; a < 3; ++a) {
-                dp[a] += wi * ci[a] * pn;
-                dr[a] += wi * ci[a] * rn;
-                fc[a] += wi * (cS * un[a] - cu * Sn[a]);
-            }
-        }
-#pragma unroll
-        for (int a = 0; a < 3; ++a) {
-            dp[a] *= 3.0;
-            dr[a] *= 3.0;
-            fc[a] *= 1.5;  // 3 (1/c_s^2) x 1/2
-        }
-        const double mu = P.mu[o];
-        const double S[3] = {P.S[o], P.S[pt + o], P.S[2 * pt + o]};
-        const double z = P.stat[o];
-        const double F[3] = {mu * dp[0] + (rho - c.rho_ref) * c.gx + (1.0 - z) * c.fbx + fc[0],
-                             mu * dp[1] + (rho - c.rho_ref) * c.gy + (1.0 - z) * c.fby + fc[1],
-                             mu * dp[2] + (rho - c.rho_ref) * c.gz + (1.0 - z) * c.fbz + fc[2]};
-        // ---- history of the previous level
-        const double php = (double)H[o];
-        const double up[3] = {(double)H[pt + o], (double)H[2 * pt + o], (double)H[3 * pt + o]};
-        const double Sp[3] = {(double)H[4 * pt + o], (double)H[5 * pt + o], (double)H[6 * pt + o]};
-        // ---- flow populations
-        const T* gp = P.pop[cur];
-        const T* fp = gp + (int64_t)Q * pt;
-        double f[Q];
-#pragma unroll
-        for (int i = 0; i < Q; ++i) f[i] = (double)fp[(int64_t)i * pt + o];
-        // ---- viscosity: nu = (1/s2a - 1/2)(1 - c_s^2)/2 = (1/s2b - 1/2) c_s^2
-        double om = 1.0 - z;
-        om = om < c.solid_eps ? c.solid_eps : om;
-        const double nu = muv_of(c, ph) / (rho * om);
-        const double ta = nu / ((1.0 - cs2) * 0.5) + 0.5, tb = nu / cs2 + 0.5;
-        const double s2a = 1.0 / ta, s2b = 1.0 / tb;
-        // ---- u*, solid force, u, P (Eqs. uStar, u)
-        double us[3], af[3], u[3];
-        if (c.first) {
-#pragma unroll
-            for (int a = 0; a < 3; ++a) us[a] = up[a];
-        } else {
-            double j[3] = {0.0, 0.0, 0.0};
-#pragma unroll
-            for (int i = 1; i < Q; ++i) {
-                j[0] += cxv(i) * f[i];
-                j[1] += cyv(i) * f[i];
-                j[2] += czv(i) * f[i];
-            }
-#pragma unroll
-            for (int a = 0; a < 3; ++a) us[a] = (j[a] + 0.5 * F[a]) / rho;
-        }
-#pragma unroll
-        for (int a = 0; a < 3; ++a) {
-            af[a] = -z * us[a];  // phi0 (u_s - u*) with u_s = 0
-            u[a] = c.first ? us[a] : us[a] + 0.5 * af[a];
-        }
-        const double udr = u[0] * dr[0] + u[1] * dr[1] + u[2] * dr[2];
-        const double Su = S[0] * u[0] + S[1] * u[1] + S[2] * u[2];
-        const double q = rho * (u[0] * u[0] + u[1] * u[1] + u[2] * u[2]) - Su;
-        const double rhop = rho_of(c, php);
-        const double qp = rhop * (up[0] * up[0] + up[1] * up[1] + up[2] * up[2]) -
-                          (Sp[0] * up[0] + Sp[1] * up[1] + Sp[2] * up[2]);
-        double Pr = 0.0;
-        if (!c.first) {
-            double sum = 0.0;
-#pragma unroll
-            for (int i = 1; i < Q; ++i) sum += f[i];
-            // H = -2 K (1 - 3 d0)(1/s2a - 1/2) (the printed 3-D factor with s0 = s2a)
-            const double Hf = -2.0 * c.K * (1.0 - 3.0 * cs2) * (ta - 0.5);
-            Pr = cs2 / (1.0 - c.w[0]) *
-                 (sum + (0.5 + Hf) * udr - c.w[0] * (rho * (u[0] * u[0] + u[1] * u[1] + u[2] * u[2]) - Su) / (1.0 - cs2) +
-                  0.5 * c.K * (q - qp));
-        }
-        if (MODE == M3_OUT) {
-            double* out = P.out;
-            out[o] = ph;
-            out[pt + o] = u[0];
-            out[2 * pt + o] = u[1];
-            out[3 * pt + o] = u[2];
-            out[4 * pt + o] = Pr;
-            // Eq. (2energy) with psi; grad psi from the static plane
-            const double* psi = P.stat + pt;
-            double gq[3] = {0.0, 0.0, 0.0};
-#pragma unroll
-            for (int i = 1; i < Q; ++i) {
-                const double v = wfd(i) * psi[nb.o[i]];
-                gq[0] += cxv(i) * v;
-                gq[1] += cyv(i) * v;
-                gq[2] += czv(i) * v;
-            }
-            const double qq = psi[o], s = c.sigma, D = c.Dw;
-            const double g2 = dp[0] * dp[0] + dp[1] * dp[1] + dp[2] * dp[2];
-            const double gpq = 3.0 * (gq[0] * dp[0] + gq[1] * dp[1] + gq[2] * dp[2]);
-            red[0] = ph;
-            red[1] = 3.0 * s / (4.0 * D) * (1.0 - ph) * (1.0 - ph) * (1.0 + ph) * (1.0 + ph) + 3.0 * D * s / 16.0 * g2 +
-                     9.0 * s / (2.0 * D) * z * z * ph * ph + 3.0 * s / D * qq * ph * (ph * ph + z * z - 1.0) +
-                     3.0 * D * s / 8.0 * gpq;
-            red[2] = 0.5 * rho * (u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
-            red[3] = (fin(ph) && fin(u[0]) && fin(u[1]) && fin(u[2]) && fin(Pr)) ? 0.0 : 1.0;
-        } else {
-            const int nxt = cur ^ 1;
-            T* gn = P.pop[nxt];
-            T* fn = gn + (int64_t)Q * pt;
-            // ---- flow collision in Hermite moments: dm_k = -s_k (m_k - m_k^eq) + (1 - s_k/2) F_k,
-            // f* = f + w_i sum_k H_k(c_i) dm_k / |H_k|^2
-            const int A6[6] = {0, 1, 2, 0, 0, 1}, B6[6] = {0, 1, 2, 1, 2, 2};
-            double M2[6];
-#pragma unroll
-            for (int k = 0; k < 6; ++k) {
-                const int a = A6[k], b = B6[k];
-                const double T_now = 0.5 * (S[a] * u[b] + u[a] * S[b]);
-                const double T_old = 0.5 * (Sp[a] * up[b] + up[a] * Sp[b]);
-                M2[k] = (u[a] * F[b] + F[a] * u[b]) - (T_now - T_old) + cs2 * (u[a] * dr[b] + dr[a] * u[b]) +
-                        (a == b ? (1.0 - 3.0 * cs2) * udr : 0.0);
-            }
-            double m[Q];
-            moments15(f, cs2, m);
-            double meq[Q], src[Q], rate[Q];
-            const double r2 = rho * 1.0;
-            meq[0] = 0.0;
-            src[0] = udr;
-            rate[0] = s2a;
-#pragma unroll
-            for (int a = 0; a < 3; ++a) {
-                meq[1 + a] = r2 * u[a];
-                src[1 + a] = F[a] + rho * af[a];
-                rate[1 + a] = c.s1;
-                meq[4 + a] = Pr + rho * u[a] * u[a] - S[a] * u[a];
-                src[4 + a] = M2[a];
-                rate[4 + a] = s2a;
-            }
-            meq[7] = rho * u[0] * u[1] - 0.5 * (S[0] * u[1] + u[0] * S[1]);
-            meq[8] = rho * u[0] * u[2] - 0.5 * (S[0] * u[2] + u[0] * S[2]);
-            meq[9] = rho * u[1] * u[2] - 0.5 * (S[1] * u[2] + u[1] * S[2]);
-            src[7] = M2[3];
-            src[8] = M2[4];
-            src[9] = M2[5];
-            rate[7] = rate[8] = rate[9] = s2b;
-#pragma unroll
-            for (int k = 10; k < 14; ++k) {
-                meq[k] = 0.0;
-                src[k] = 0.0;
-                rate[k] = c.s3;
-            }
-            meq[14] = -2.0 * cs2 * Pr;
-            src[14] = 0.0;
-            rate[14] = s2a;
-            double dm[Q];
-#pragma unroll
-            for (int k = 0; k < Q; ++k) dm[k] = (-rate[k] * (m[k] - meq[k]) + (1.0 - 0.5 * rate[k]) * src[k]) * c.inv_norm[k];
-            double df[Q];
-            inverse15(dm, cs2, df);
-#pragma unroll
-            for (int i = 0; i < Q; ++i) fn[(int64_t)i * pt + nb.o[i]] = (T)(f[i] + wgt(c, i) * df[i]);
-            // ---- phase-field collision (Sec. 3.1)
-            double g[Q];
-            g[0] = php + (double)gp[o];
-#pragma unroll
-            for (int i = 1; i < Q; ++i) g[i] = (double)gp[(int64_t)i * pt + o];
-            double mg[Q];
-            moments15(g, cs2, mg);
-            const double em = c.eta * mu;
-            double geq[Q], gsrc[Q];
-            geq[0] = ph;
-            gsrc[0] = 0.0;
-#pragma unroll
-            for (int a = 0; a < 3; ++a) {
-                geq[1 + a] = ph * u[a];
-                gsrc[1 + a] = ph * u[a] - php * up[a];  // d_t(phi u), backward difference
-                geq[4 + a] = -cs2 * (ph - em);
-                gsrc[4 + a] = 0.0;
-            }
-#pragma unroll
-            for (int k = 7; k < 14; ++k) {
-                geq[k] = 0.0;
-                gsrc[k] = 0.0;
-            }
-            geq[14] = 2.0 * cs2 * cs2 * (ph - em);
-            gsrc[14] = 0.0;
-#pragma unroll
-            for (int k = 0; k < Q; ++k)
-                dm[k] = (-c.sg[k] * (mg[k] - geq[k]) + (1.0 - 0.5 * c.sg[k]) * gsrc[k]) * c.inv_norm[k];
-            const T phs = (T)ph;  // the history value g_0 is stored against
-            double dg[Q];
-            inverse15(dm, cs2, dg);
-#pragma unroll
-            for (int i = 0; i < Q; ++i) {
-                const double gi = g[i] + wgt(c, i) * dg[i];
-                if (i == 0)
-                    gn[o] = (T)(gi - (double)phs);
-                else
-                    gn[(int64_t)i * pt + nb.o[i]] = (T)gi;
-            }
-            // ---- history of this level
-            T* Hn = P.hist[nxt];
-            Hn[o] = phs;
-#pragma unroll
-            for (int a = 0; a < 3; ++a) {
-                Hn[(1 + a) * pt + o] = (T)u[a];
-                Hn[(4 + a) * pt + o] = (T)S[a];
-            }
-        }
+        const NbPlanes<T> A{P.phi, P.S, P.hist[cur] + c.pitch, c.pitch};
+        node_body<T, MODE>(c, P, cur, o, nb, A, red);
     }
     if (MODE == M3_OUT) block_sums(red, P.part);
+}
+
+// The node update marching along z: a block owns an MX x MY column of nodes
+// over MZ slices and keeps three slices (z - 1, z, z + 1) of the order
+// parameter, S and the lagged velocity on the column and its one-node ring in
+// LDS, loading one new slice per step along z.  Every value it reads there is
+// the one the plane holds; only where it comes from differs from k3_node.
+template <class T>
+__global__ __launch_bounds__(NT) void k3_march(Coef3 c, Planes3<T> P, int cur, int ntx, int nty) {
+    __shared__ double s_phi[3][MP];
+    __shared__ double s_S[3][3 * MP];
+    __shared__ T s_u[3][3 * MP];
+    int b = blockIdx.x;
+    const int tx = b % ntx;
+    b /= ntx;
+    const int ty = b % nty;
+    const int z0 = (b / nty) * MZ;
+    const int z1 = z0 + MZ < c.nz ? z0 + MZ : c.nz;
+    const int x0 = tx * MX, y0 = ty * MY;
+    const int t = threadIdx.x;
+    const int x = x0 + (t % MX), y = y0 + t / MX;
+    const bool in = x < c.nx && y < c.ny;
+    const int64_t pt = c.pitch;
+    const T* U = P.hist[cur] + pt;
+    // in-slice offsets of the ring points this thread loads (two rounds);
+    // columns and rows past the ring a ragged or narrow tile needs are
+    // clamped into the grid and never read
+    int off[2];
+#pragma unroll
+    for (int r = 0; r < 2; ++r) {
+        const int p = t + r * NT < MP ? t + r * NT : MP - 1;
+        int gx = x0 + p % MW - 1, gy = y0 + p / MW - 1;
+        gx = gx < 0 ? gx + c.nx : (gx >= c.nx ? gx - c.nx : gx);
+        gy = gy < 0 ? gy + c.ny : (gy >= c.ny ? gy - c.ny : gy);
+        gx = gx < c.nx ? gx : c.nx - 1;
+        gy = gy < c.ny ? gy : c.ny - 1;
+        off[r] = gy * c.nx + gx;
+    }
+    auto load = [&](int zz, int slot) {
+        const int64_t base = (int64_t)zz * c.nx * c.ny;
+#pragma unroll
+        for (int r = 0; r < 2; ++r) {
+            const int p = t + r * NT;
+            if (p < MP) {
+                const int64_t n = base + off[r];
+                s_phi[slot][p] = P.phi[n];
+#pragma unroll
+                for (int k = 0; k < 3; ++k) {
+                    s_S[slot][k * MP + p] = (double)P.S[k * pt + n];
+                    s_u[slot][k * MP + p] = U[k * pt + n];
+                }
+            }
+        }
+    };
+    load(z0 == 0 ? c.nz - 1 : z0 - 1, 0);
+    load(z0, 1);
+    double red[NPART3];
+    for (int k = 0; z0 + k < z1; ++k) {
+        const int z = z0 + k;
+        if (k > 0) __syncthreads();  // step k - 1 is done with the slot loaded next
+        const int sm = k % 3, s0 = (k + 1) % 3, sp = (k + 2) % 3;
+        load(z + 1 == c.nz ? 0 : z + 1, sp);
+        __syncthreads();
+        if (in) {
+            Nb nb;
+            neighbours_xyz(c, x, y, z, nb);
+            const int q = (t / MX + 1) * MW + (t % MX) + 1;
+            const NbLds<T> A{{s_phi[sm], s_phi[s0], s_phi[sp]}, {s_S[sm], s_S[s0], s_S[sp]}, {s_u[sm], s_u[s0], s_u[sp]}, q};
+            node_body<T, M3_STEP>(c, P, cur, ((int64_t)z * c.ny + y) * c.nx + x, nb, A, red);
+        }
+    }
 }
 
 // Equilibria of the initial state (procedure step 1): g = g^eq(phi, mu, u),
@@ -668,18 +805,22 @@ void fill_coef3(const lbm3_params& p, const Sizes3& z, Coef3& c) {
     c.fbx = p.fbx; c.fby = p.fby; c.fbz = p.fbz; c.solid_eps = p.solid_eps;
     const double s1p = 1.0 / p.tau_phi;
     const double sg[Q] = {p.s0, s1p, s1p, s1p, p.s2, p.s2, p.s2, p.s2, p.s2, p.s2, p.s3, p.s3, p.s3, p.s3, p.s4};
-    for (int k = 0; k < Q; ++k) c.sg[k] = sg[k];
     c.s1 = p.s1; c.s3 = p.s3;
-    // norms of the Hermite rows under the weights
-    for (int k = 0; k < Q; ++k) {
+    // norms of the Hermite rows under the weights, one row per class (the
+    // others of a class are its images under the lattice's symmetries)
+    const int first_of_class[7] = {0, 1, 4, 7, 10, 13, 14};
+    for (int j = 0; j < 7; ++j) {
+        const int k = first_of_class[j];
         double s = 0.0;
         for (int i = 0; i < Q; ++i) {
             const double w = i == 0 ? c.w[0] : (i <= 6 ? c.w[1] : c.w[2]);
             const double h = hrow(k, cxv(i), cyv(i), czv(i), cs2);
             s += w * h * h;
         }
-        c.inv_norm[k] = 1.0 / s;
+        c.inv_norm[j] = 1.0 / s;
+        c.gA[j] = -sg[k] * c.inv_norm[j];
     }
+    c.gB1 = (1.0 - 0.5 * sg[1]) * c.inv_norm[1];
 }
 
 template <class T>
@@ -717,7 +858,9 @@ int step3(lbm3_domain* d, int64_t nsteps) {
         int rc = fields3<T>(d);
         if (rc) return rc;
         Planes3<T> P = planes<T>(d);
-        hipLaunchKernelGGL((k3_node<T, M3_STEP>), dim3((unsigned)d->blocks), dim3(NT), 0, d->stream, d->c, P, d->cur);
+        const int ntx = (d->c.nx + MX - 1) / MX, nty = (d->c.ny + MY - 1) / MY, nzc = (d->c.nz + MZ - 1) / MZ;
+        hipLaunchKernelGGL(k3_march<T>, dim3((unsigned)((int64_t)ntx * nty * nzc)), dim3(NT), 0, d->stream, d->c, P,
+                           d->cur, ntx, nty);
         HIPCHK3(hipGetLastError());
         d->cur ^= 1;
         d->c.first = 0;
