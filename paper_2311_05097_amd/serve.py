@@ -13,7 +13,9 @@ workspaces together fit the GPU's last-level cache (``lane_bytes``); a tick
 steps the lanes one after another on one stream, each with one fused launch
 per time step over the tiles of all its members (replayed from a HIP graph).
 One batch over everything would stream the whole resident set from HBM every
-step; a lane's set stays in the cache for its steps.
+step; a lane's set stays in the cache for its steps.  Lanes on separate
+streams, running together, measured 3-11% slower: together they no longer fit
+the cache.
 
 ``run_solo`` is the baseline: the same stream processed one job at a time, each
 with its own per-step launches (no batching, no graph).
