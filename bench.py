@@ -105,7 +105,7 @@ def bytes_per_lup_3d(storage: str) -> int:
 
 def run_gpu3(workload, storage: str, steps: int, warmup: int, samples: int = 5):
     """As run_gpu, for a 3-D domain (lbmgls3d.h): per-step kernel time is the
-    HIP-event time of each slice's step sequence (all four kernels)."""
+    HIP-event time of each slice's step sequence (all the kernels of a step)."""
     import numpy as np
     import torch
     from paper_2311_05097_amd import lbmgls
@@ -524,7 +524,7 @@ def main():
                                  "ms_per_step": round(e["ms_per_step"], 5),
                                  "mass_drift": e["mass_drift"], "finite": e["finite"]}
         # the three-dimensional path: 256^3 drop on a slab, FP32 and FP64
-        # storage (FP64 arithmetic), four kernels per step
+        # storage (FP64 arithmetic), three kernels per step
         w3 = W.bench_3d()
         for st in ("fp32", "fp64"):
             e = run_gpu3(w3, st, 200, 20)

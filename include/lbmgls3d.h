@@ -82,8 +82,8 @@ int lbm3_create(const lbm3_params *p, void *dev_workspace, size_t bytes, void *h
                 const double *phi0, const double *cos_theta, const double *ux, const double *uy,
                 const double *uz, lbm3_domain **out);
 
-/* Procedure steps 2-6, nsteps >= 0 times; four kernels per step (order
- * parameter, chemical potential, mass flux, then the node update: gradients,
+/* Procedure steps 2-6, nsteps >= 0 times; three kernels per step (order
+ * parameter, chemical potential, then the node update: mass flux, gradients,
  * F_c, forces, velocity and pressure recovery, both collisions, streaming).
  * Enqueued; returns without waiting. */
 int lbm3_step(lbm3_domain *d, int64_t nsteps);

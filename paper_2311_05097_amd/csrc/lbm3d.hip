@@ -1,18 +1,19 @@
 // lbm3d.hip -- three-dimensional path of the library (C ABI in lbmgls3d.h):
 // the phase-field and flow lattice Boltzmann models of Sec. 3.1-3.2 on a
-// 15-velocity lattice, four kernels per time step.
+// 15-velocity lattice, three kernels per time step.
 //
-// Why four kernels and not one fused tile kernel as in two dimensions: the
+// Why three kernels and not one fused tile kernel as in two dimensions: the
 // node update needs the order parameter on a 3-node ring (mu needs its
 // Laplacian, the mass flux S the gradient of mu, F_c the divergence of a
 // tensor built from S).  In 3-D a 64 x 4 x 4 block would have to rebuild the
 // order parameter from 15 populations at ~7x as many ring nodes as it owns.
-// Instead the order parameter, mu and S are written once per step as FP64
-// planes (8 + 8 + 24 bytes per node); mu and S read their one-node rings
-// through the caches, and the node update (k3_march) marches along z over a
-// 64 x 4 column, holding three slices of phi, S and the lagged velocity with
-// their ring in LDS, so that each of those values is read from memory about
-// 1.3 times per step instead of once per neighbour that needs it.
+// Instead the order parameter and mu are written once per step as FP64
+// planes (8 + 8 bytes per node; mu reads its one-node ring of phi through the
+// caches), and the node update (k3_march) marches along z over a 64 x 4
+// column, holding slices of phi and the lagged velocity on the one-node ring
+// and of mu on the two-node ring in LDS, forming S on the ring there, so
+// that each of those values is read from memory under twice per step instead
+// of once per neighbour that needs it.
 //
 // Arithmetic is FP64 for either storage; FP32 storage rounds what is stored.
 //
@@ -267,25 +268,38 @@ __global__ __launch_bounds__(NT) void k3_mu(Coef3 c, Planes3<T> P) {
     P.mu[o] = a * f * (f - 1.0) * (f + 1.0) - b * lap + 3.0 * a * z * z * f + a * q * (3.0 * f * f + z * z - 1.0) - b * lq;
 }
 
-// Consistent mass flux S = M grad(mu) (rho1 - rho2)/2.
+// Consistent mass flux S = M grad(mu) (rho1 - rho2)/2 at one node from mu at
+// its neighbours (mu_at(i): mu at x + c_i); every kernel that forms S uses
+// this, so the sums and their order are the same wherever S is formed.
+template <class F>
+__device__ __forceinline__ void flux_of(const Coef3& c, F mu_at, double S[3]) {
+    double gx = 0.0, gy = 0.0, gz = 0.0;
+#pragma unroll
+    for (int i = 1; i < Q; ++i) {
+        const double v = wfd(i) * mu_at(i);
+        gx += cxv(i) * v;
+        gy += cyv(i) * v;
+        gz += czv(i) * v;
+    }
+    const double k = 3.0 * c.Mob * (c.rho1 - c.rho2) * 0.5;
+    S[0] = k * gx;
+    S[1] = k * gy;
+    S[2] = k * gz;
+}
+
+// S planes of the current level (for creation and the output pass; the
+// marching node update forms S itself)
 template <class T>
 __global__ __launch_bounds__(NT) void k3_flux(Coef3 c, Planes3<T> P) {
     const int64_t o = (int64_t)blockIdx.x * NT + threadIdx.x;
     if (o >= c.n) return;
     Nb nb;
     neighbours(c, o, nb);
-    double gx = 0.0, gy = 0.0, gz = 0.0;
-#pragma unroll
-    for (int i = 1; i < Q; ++i) {
-        const double v = wfd(i) * P.mu[nb.o[i]];
-        gx += cxv(i) * v;
-        gy += cyv(i) * v;
-        gz += czv(i) * v;
-    }
-    const double k = 3.0 * c.Mob * (c.rho1 - c.rho2) * 0.5;
-    P.S[o] = k * gx;
-    P.S[c.pitch + o] = k * gy;
-    P.S[2 * c.pitch + o] = k * gz;
+    double S[3];
+    flux_of(c, [&](int i) { return P.mu[nb.o[i]]; }, S);
+    P.S[o] = S[0];
+    P.S[c.pitch + o] = S[1];
+    P.S[2 * c.pitch + o] = S[2];
 }
 
 enum { M3_STEP = 0, M3_OUT = 1 };
@@ -335,8 +349,9 @@ struct NbPlanes {
     __device__ __forceinline__ T v(int i, int k, const Nb& nb) const { return u[k * pt + nb.o[i]]; }
 };
 
-constexpr int MX = 64, MY = NT / MX, MZ = 8;  // marching column and slices per block
+constexpr int MX = 64, MY = NT / MX, MZ = 16;  // marching column and slices per block
 constexpr int MW = MX + 2, MP = MW * (MY + 2);  // LDS slice with the one-node ring
+constexpr int MW2 = MX + 4, MP2 = MW2 * (MY + 4);  // with the two-node ring
 
 template <class T>
 struct NbLds {
@@ -594,13 +609,16 @@ __global__ __launch_bounds__(NT) void k3_node(Coef3 c, Planes3<T> P, int cur) {
 // The node update marching along z: a block owns an MX x MY column of nodes
 // over MZ slices and keeps three slices (z - 1, z, z + 1) of the order
 // parameter, S and the lagged velocity on the column and its one-node ring in
-// LDS, loading one new slice per step along z.  Every value it reads there is
-// the one the plane holds; only where it comes from differs from k3_node.
+// LDS, loading one new slice per step along z.  S is formed here, on the ring
+// of each new slice, from three slices of mu on the two-node ring (also in
+// LDS), with the sums k3_flux makes.  Every value the node update reads is
+// the one k3_node would read; only where it comes from differs.
 template <class T>
 __global__ __launch_bounds__(NT) void k3_march(Coef3 c, Planes3<T> P, int cur, int ntx, int nty) {
     __shared__ double s_phi[3][MP];
     __shared__ double s_S[3][3 * MP];
     __shared__ T s_u[3][3 * MP];
+    __shared__ double s_mu[3][MP2];
     int b = blockIdx.x;
     const int tx = b % ntx;
     b /= ntx;
@@ -613,22 +631,28 @@ __global__ __launch_bounds__(NT) void k3_march(Coef3 c, Planes3<T> P, int cur, i
     const bool in = x < c.nx && y < c.ny;
     const int64_t pt = c.pitch;
     const T* U = P.hist[cur] + pt;
-    // in-slice offsets of the ring points this thread loads (two rounds);
-    // columns and rows past the ring a ragged or narrow tile needs are
-    // clamped into the grid and never read
-    int off[2];
-#pragma unroll
-    for (int r = 0; r < 2; ++r) {
-        const int p = t + r * NT < MP ? t + r * NT : MP - 1;
-        int gx = x0 + p % MW - 1, gy = y0 + p / MW - 1;
+    // in-slice offsets of the ring points this thread loads: the one-node
+    // ring (two rounds) and the two-node ring (three rounds); columns and rows
+    // past the ring a ragged or narrow tile needs are clamped into the grid
+    // and never read
+    auto ring_off = [&](int p, int w, int h) {
+        int gx = x0 + p % w - h, gy = y0 + p / w - h;
         gx = gx < 0 ? gx + c.nx : (gx >= c.nx ? gx - c.nx : gx);
         gy = gy < 0 ? gy + c.ny : (gy >= c.ny ? gy - c.ny : gy);
         gx = gx < c.nx ? gx : c.nx - 1;
         gy = gy < c.ny ? gy : c.ny - 1;
-        off[r] = gy * c.nx + gx;
-    }
-    auto load = [&](int zz, int slot) {
-        const int64_t base = (int64_t)zz * c.nx * c.ny;
+        return gy * c.nx + gx;
+    };
+    int off[2], off2[3];
+#pragma unroll
+    for (int r = 0; r < 2; ++r) off[r] = ring_off(t + r * NT < MP ? t + r * NT : MP - 1, MW, 1);
+#pragma unroll
+    for (int r = 0; r < 3; ++r) off2[r] = ring_off(t + r * NT < MP2 ? t + r * NT : MP2 - 1, MW2, 2);
+    auto wrapz = [&](int zz) { return zz < 0 ? zz + c.nz : (zz >= c.nz ? zz - c.nz : zz); };
+    // slots: phi, S and u of slice s in (s - z0 + 1) % 3, mu of slice s in (s - z0 + 3) % 3
+    auto load = [&](int s) {
+        const int slot = (s - z0 + 1) % 3;
+        const int64_t base = (int64_t)wrapz(s) * c.nx * c.ny;
 #pragma unroll
         for (int r = 0; r < 2; ++r) {
             const int p = t + r * NT;
@@ -636,26 +660,59 @@ __global__ __launch_bounds__(NT) void k3_march(Coef3 c, Planes3<T> P, int cur, i
                 const int64_t n = base + off[r];
                 s_phi[slot][p] = P.phi[n];
 #pragma unroll
-                for (int k = 0; k < 3; ++k) {
-                    s_S[slot][k * MP + p] = (double)P.S[k * pt + n];
-                    s_u[slot][k * MP + p] = U[k * pt + n];
-                }
+                for (int k = 0; k < 3; ++k) s_u[slot][k * MP + p] = U[k * pt + n];
             }
         }
     };
-    load(z0 == 0 ? c.nz - 1 : z0 - 1, 0);
-    load(z0, 1);
+    auto load_mu = [&](int s) {
+        const int slot = (s - z0 + 3) % 3;
+        const int64_t base = (int64_t)wrapz(s) * c.nx * c.ny;
+#pragma unroll
+        for (int r = 0; r < 3; ++r) {
+            const int p = t + r * NT;
+            if (p < MP2) s_mu[slot][p] = P.mu[base + off2[r]];
+        }
+    };
+    auto flux = [&](int s) {  // S of slice s on the ring, from mu of slices s - 1, s, s + 1
+        const double* m3[3] = {s_mu[(s - z0 + 2) % 3], s_mu[(s - z0 + 3) % 3], s_mu[(s - z0 + 4) % 3]};
+        double* S = s_S[(s - z0 + 1) % 3];
+#pragma unroll
+        for (int r = 0; r < 2; ++r) {
+            const int p = t + r * NT;
+            if (p < MP) {
+                const int q2 = (p / MW + 1) * MW2 + (p % MW) + 1;
+                double v[3];
+                flux_of(c, [&](int i) { return m3[czv(i) + 1][q2 + cyv(i) * MW2 + cxv(i)]; }, v);
+#pragma unroll
+                for (int k = 0; k < 3; ++k) S[k * MP + p] = v[k];
+            }
+        }
+    };
+    load(z0 - 1);
+    load(z0);
+    load_mu(z0 - 2);
+    load_mu(z0 - 1);
+    load_mu(z0);
+    __syncthreads();
+    flux(z0 - 1);
+    __syncthreads();
+    load_mu(z0 + 1);  // into the slot of z0 - 2
+    __syncthreads();
+    flux(z0);
     double red[NPART3];
     for (int k = 0; z0 + k < z1; ++k) {
         const int z = z0 + k;
-        if (k > 0) __syncthreads();  // step k - 1 is done with the slot loaded next
-        const int sm = k % 3, s0 = (k + 1) % 3, sp = (k + 2) % 3;
-        load(z + 1 == c.nz ? 0 : z + 1, sp);
+        __syncthreads();  // the slots written next are no longer read
+        load(z + 1);
+        load_mu(z + 2);
+        __syncthreads();
+        flux(z + 1);
         __syncthreads();
         if (in) {
             Nb nb;
             neighbours_xyz(c, x, y, z, nb);
             const int q = (t / MX + 1) * MW + (t % MX) + 1;
+            const int sm = k % 3, s0 = (k + 1) % 3, sp = (k + 2) % 3;
             const NbLds<T> A{{s_phi[sm], s_phi[s0], s_phi[sp]}, {s_S[sm], s_S[s0], s_S[sp]}, {s_u[sm], s_u[s0], s_u[sp]}, q};
             node_body<T, M3_STEP>(c, P, cur, ((int64_t)z * c.ny + y) * c.nx + x, nb, A, red);
         }
@@ -839,14 +896,15 @@ Planes3<T> planes(lbm3_domain* d) {
     return P;
 }
 
-// phi of the current level from the populations, then mu and S
+// phi of the current level from the populations, then mu, and S unless the
+// marching node update forms it
 template <class T>
-int fields3(lbm3_domain* d) {
+int fields3(lbm3_domain* d, bool with_S) {
     Planes3<T> P = planes<T>(d);
     const dim3 g((unsigned)d->blocks), b(NT);
     hipLaunchKernelGGL(k3_phi<T>, g, b, 0, d->stream, d->c, P, d->cur);
     hipLaunchKernelGGL(k3_mu<T>, g, b, 0, d->stream, d->c, P);
-    hipLaunchKernelGGL(k3_flux<T>, g, b, 0, d->stream, d->c, P);
+    if (with_S) hipLaunchKernelGGL(k3_flux<T>, g, b, 0, d->stream, d->c, P);
     HIPCHK3(hipGetLastError());
     return LBM_OK;
 }
@@ -855,7 +913,7 @@ template <class T>
 int step3(lbm3_domain* d, int64_t nsteps) {
     HIPCHK3(hipEventRecord(d->ev0, d->stream));
     for (int64_t s = 0; s < nsteps; ++s) {
-        int rc = fields3<T>(d);
+        int rc = fields3<T>(d, false);
         if (rc) return rc;
         Planes3<T> P = planes<T>(d);
         const int ntx = (d->c.nx + MX - 1) / MX, nty = (d->c.ny + MY - 1) / MY, nzc = (d->c.nz + MZ - 1) / MZ;
@@ -874,7 +932,7 @@ int step3(lbm3_domain* d, int64_t nsteps) {
 // macroscopic pass of the current level into `out` and the block sums
 template <class T>
 int out3(lbm3_domain* d, double res[NPART3]) {
-    int rc = fields3<T>(d);
+    int rc = fields3<T>(d, true);
     if (rc) return rc;
     Planes3<T> P = planes<T>(d);
     hipLaunchKernelGGL((k3_node<T, M3_OUT>), dim3((unsigned)d->blocks), dim3(NT), 0, d->stream, d->c, P, d->cur);
