@@ -94,9 +94,11 @@ class Server:
         self.storage = storage
         self.budget = int(budget_bytes)
         self.tick = int(tick_steps)
-        # tile 0: the autotuner's shape for this storage on a 512^2 job (the
-        # stream's median side); one shape serves every member of a lane
-        self.tile = int(tile) if tile else _tuned_tile(512, storage)
+        # tile 0: the autotuner's shape for this storage on a 1024^2 job, the
+        # size of a lane (~1M nodes, its working set in the last-level cache);
+        # one shape serves every member of a lane (lanes of 128^2 to 1024^2
+        # jobs measured fastest in it: FP32 64x4, 4% above 64x8; FP16 64x8)
+        self.tile = int(tile) if tile else _tuned_tile(1024, storage)
         self.keep_phi = keep_phi
         self.overrides = dict(job_overrides or {})
         self.on_retire = on_retire
