@@ -197,6 +197,23 @@ def measured_traffic(workload: str, storage: str, tile: int):
     return None if e is None else e["bytes_per_launch"]
 
 
+def kernel_source_hash3() -> str:
+    h = hashlib.sha256(open(os.path.join(ROOT, "paper_2311_05097_amd/csrc/lbm3d.hip"), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic3(storage: str):
+    """Bytes per step of the 3-D step kernels on the 256^3 workload from
+    committed rocprofv3 counter runs, if taken on the current 3-D source."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    t = json.load(open(TRAFFIC_FILE)).get("d3", {})
+    if t.get("source_hash") != kernel_source_hash3():
+        return None
+    e = t.get("entries", {}).get(storage)
+    return None if e is None else e["bytes_per_step"]
+
+
 def cpu_baseline():
     """The FP64 CPU oracle, unchanged, built for this host (-O3 -march=native)
     and timed on a bounded sample of the same 1024 x 1024 workload: the median
@@ -407,7 +424,8 @@ def main():
             "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": DTYPE[args.storage],
             "data": "synthetic (seeded tanh geometry, no dataset)",
             "config": {"workload": w3.name, "nx": 256, "ny": 256, "nz": 256, "storage": args.storage},
-            "roofline": roofline3(args.storage, r["nodes"], r["kernel_ms"], samples=r["kernel_ms_samples"]),
+            "roofline": roofline3(args.storage, r["nodes"], r["kernel_ms"], samples=r["kernel_ms_samples"],
+                                  traffic=measured_traffic3(args.storage) if r["nodes"] == 256 ** 3 else None),
             "mass_drift": r["mass_drift"], "finite": r["finite"]}), flush=True)
         return
     w = {"c2": W.config2, "r4096": W.roofline_grid, "c5": W.pool_with_particles,
@@ -530,7 +548,8 @@ def main():
             e = run_gpu3(w3, st, 200, 20)
             extra[f"D3_256_{st}"] = {"mlups": round(e["mlups"], 1), "ms_per_step": round(e["ms_per_step"], 5),
                                      "roofline": roofline3(st, e["nodes"], e["kernel_ms"],
-                                                           samples=e["kernel_ms_samples"]),
+                                                           samples=e["kernel_ms_samples"],
+                                                           traffic=measured_traffic3(st)),
                                      "mass_drift": e["mass_drift"], "finite": e["finite"]}
         # voxel solid smoothing (20 Cahn-Hilliard steps, FP64) of a 4096^2
         # binary solid: wall time of the whole call, host copies included
