@@ -321,6 +321,16 @@ __device__ __forceinline__ constexpr int opposite(int i) {
 // Node offsets are 32-bit (domains hold fewer than 2^31 nodes); each plane
 // base is a uniform pointer, so loads use a scalar base plus a 32-bit vector
 // offset.
+// Global-address-space view of a device pointer.  The planes reach the
+// kernels through the job table, so the compiler cannot tell that they are
+// device memory and would access them with flat instructions, which also
+// count against the LDS wait counter: every wait for an LDS read would then
+// wait for the population loads in flight as well.
+template <class T>
+__device__ __forceinline__ __attribute__((address_space(1))) T* G(T* p) {
+    return (__attribute__((address_space(1))) T*)p;
+}
+
 template <class S> struct Access;
 
 template <class Sf>
@@ -328,14 +338,14 @@ struct AccessFull {  // FP64 / FP32: plain values
     using R = typename Sf::R;
     using Pop = typename Sf::Pop;
     static __device__ __forceinline__ R phi(const Pop& P, int64_t pitch, uint32_t o, const Coef<R>&) {
-        const R* p = P.p;
+        const __attribute__((address_space(1))) R* p = G(P.p);
         return ((p[o] + (p[pitch + o] + p[3 * pitch + o])) + (p[2 * pitch + o] + p[4 * pitch + o]))
              + ((p[5 * pitch + o] + p[7 * pitch + o]) + (p[6 * pitch + o] + p[8 * pitch + o]));
     }
     static __device__ __forceinline__ void load_g(const Pop& P, int64_t pitch, uint32_t o, const Coef<R>&,
                                                   R* g, int64_t& mfix) {
 #pragma unroll
-        for (int i = 0; i < 9; ++i) g[i] = P.p[i * pitch + o];
+        for (int i = 0; i < 9; ++i) g[i] = G(P.p)[i * pitch + o];
         mfix = 0;
     }
     static __device__ __forceinline__ R phi_of(const R* g, int64_t, const Coef<R>&) {
@@ -344,14 +354,14 @@ struct AccessFull {  // FP64 / FP32: plain values
     static __device__ __forceinline__ void load_f(const Pop& P, int64_t pitch, uint32_t o, const Coef<R>&,
                                                   R* f) {
 #pragma unroll
-        for (int i = 0; i < 9; ++i) f[i] = P.p[(9 + i) * pitch + o];
+        for (int i = 0; i < 9; ++i) f[i] = G(P.p)[(9 + i) * pitch + o];
     }
     static __device__ __forceinline__ void store(const Pop& P, int64_t pitch, const uint32_t* dst,
                                                  const Coef<R>&, const R* g, const R* f, int64_t) {
 #pragma unroll
-        for (int i = 0; i < 9; ++i) P.p[i * pitch + dst[i]] = g[i];
+        for (int i = 0; i < 9; ++i) G(P.p)[i * pitch + dst[i]] = g[i];
 #pragma unroll
-        for (int i = 0; i < 9; ++i) P.p[(9 + i) * pitch + dst[i]] = f[i];
+        for (int i = 0; i < 9; ++i) G(P.p)[(9 + i) * pitch + dst[i]] = f[i];
     }
     // next to walls: the crossing directions go to the opposite planes at o
     static __device__ __forceinline__ void store_bb(const Pop& P, int64_t pitch, const uint32_t* dst,
@@ -362,8 +372,8 @@ struct AccessFull {  // FP64 / FP32: plain values
             const bool cr = crosses(i, bb);
             const int64_t pl = cr ? opposite(i) : i;
             const uint32_t d = cr ? o : dst[i];
-            P.p[pl * pitch + d] = g[i];
-            P.p[(9 + pl) * pitch + d] = f[i];
+            G(P.p)[pl * pitch + d] = g[i];
+            G(P.p)[(9 + pl) * pitch + d] = f[i];
         }
     }
 };
@@ -391,16 +401,16 @@ struct AccessHalf {  // 16-bit codes + fixed-point rest population
     static __device__ __forceinline__ float phi(const Pop& P, int64_t pitch, uint32_t o, const Coef<float>& c) {
         double s = 0.0;
 #pragma unroll
-        for (int i = 0; i < 8; ++i) s += gfix(c, P.gm[i * pitch + o]);
-        return fix2f(P.g0[o] + (int64_t)s);
+        for (int i = 0; i < 8; ++i) s += gfix(c, G(P.gm)[i * pitch + o]);
+        return fix2f(G(P.g0)[o] + (int64_t)s);
     }
     static __device__ __forceinline__ void load_g(const Pop& P, int64_t pitch, uint32_t o, const Coef<float>& c,
                                                   float* g, int64_t& mfix) {
-        const int64_t rest = P.g0[o];
+        const int64_t rest = G(P.g0)[o];
         double s = 0.0;
 #pragma unroll
         for (int i = 0; i < 8; ++i) {
-            const uint16_t code = P.gm[i * pitch + o];
+            const uint16_t code = G(P.gm)[i * pitch + o];
             g[i + 1] = Sh::dec(code) * c.isg;
             s += gfix(c, code);
         }
@@ -413,7 +423,7 @@ struct AccessHalf {  // 16-bit codes + fixed-point rest population
     static __device__ __forceinline__ void load_f(const Pop& P, int64_t pitch, uint32_t o, const Coef<float>& c,
                                                   float* f) {
 #pragma unroll
-        for (int i = 0; i < 9; ++i) f[i] = Sh::dec(P.fm[i * pitch + o]) * c.isf;
+        for (int i = 0; i < 9; ++i) f[i] = Sh::dec(G(P.fm)[i * pitch + o]) * c.isf;
     }
     // mfix: the node's conserved sum_i g_i in fixed point; g_0 is written so
     // that the stored values sum to it exactly.
@@ -424,12 +434,12 @@ struct AccessHalf {  // 16-bit codes + fixed-point rest population
 #pragma unroll
         for (int i = 0; i < 8; ++i) {
             const uint16_t code = Sh::enc(g[i + 1] * c.sg);
-            P.gm[i * pitch + dst[i + 1]] = code;
+            G(P.gm)[i * pitch + dst[i + 1]] = code;
             s += gfix(c, code);
         }
-        P.g0[dst[0]] = mfix - (int64_t)s;
+        G(P.g0)[dst[0]] = mfix - (int64_t)s;
 #pragma unroll
-        for (int i = 0; i < 9; ++i) P.fm[i * pitch + dst[i]] = Sh::enc(f[i] * c.sf);
+        for (int i = 0; i < 9; ++i) G(P.fm)[i * pitch + dst[i]] = Sh::enc(f[i] * c.sf);
     }
     // next to walls: the crossing directions go to the opposite planes at o
     // (dst[0] == o); the stored values still sum to mfix at this node's share
@@ -442,15 +452,15 @@ struct AccessHalf {  // 16-bit codes + fixed-point rest population
             const bool cr = crosses(i + 1, bb);
             const int64_t pl = cr ? opposite(i + 1) : i + 1;
             const uint16_t code = Sh::enc(g[i + 1] * c.sg);
-            P.gm[(pl - 1) * pitch + (cr ? o : dst[i + 1])] = code;
+            G(P.gm)[(pl - 1) * pitch + (cr ? o : dst[i + 1])] = code;
             s += gfix(c, code);
         }
-        P.g0[dst[0]] = mfix - (int64_t)s;
+        G(P.g0)[dst[0]] = mfix - (int64_t)s;
 #pragma unroll
         for (int i = 0; i < 9; ++i) {
             const bool cr = crosses(i, bb);
             const int64_t pl = cr ? opposite(i) : i;
-            P.fm[pl * pitch + (cr ? o : dst[i])] = Sh::enc(f[i] * c.sf);
+            G(P.fm)[pl * pitch + (cr ? o : dst[i])] = Sh::enc(f[i] * c.sf);
         }
     }
 };
@@ -530,8 +540,8 @@ __global__ __launch_bounds__(TileCfg<TY>::NT) void k_tile(const Job<S>* __restri
     const bool first = (step == 0);
     const Coef<R>& c = J.c;
     const typename S::Pop cur = J.pop[par];
-    const R* __restrict__ hprev = J.hist[par];
-    const R* __restrict__ st = J.stat;
+    const __attribute__((address_space(1))) R* __restrict__ hprev = G(J.hist[par]);
+    const __attribute__((address_space(1))) R* __restrict__ st = G(J.stat);
     const int x0 = te.x0, y0 = te.y0;
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     // walls this tile can see: only tiles whose 3-node halo reaches past the
@@ -562,7 +572,7 @@ __global__ __launch_bounds__(TileCfg<TY>::NT) void k_tile(const Job<S>* __restri
         own[k] = o;
         RX* sp = &sphi[(ly + 3) * W3 + lane + 3];
         if (MODE == MODE_INIT) {
-            *sp = (RX)J.in[o];
+            *sp = (RX)G(J.in)[o];
         } else if (KEEP) {
             const int kk = KEEP ? k : 0;
             A::load_g(cur, pitch, o, c, g[kk], mfix[kk]);
@@ -589,7 +599,7 @@ __global__ __launch_bounds__(TileCfg<TY>::NT) void k_tile(const Job<S>* __restri
         }
         const uint32_t o = (uint32_t)(s_row[ly] + s_col[lx]);
         if (MODE == MODE_INIT)
-            sphi[ly * W3 + lx] = (RX)J.in[o];
+            sphi[ly * W3 + lx] = (RX)G(J.in)[o];
         else if (S::kRel)
             sphi[ly * W3 + lx] = (RX)hprev[o] + (RX)A::phi(cur, pitch, o, c);
         else
@@ -737,7 +747,7 @@ __global__ __launch_bounds__(TileCfg<TY>::NT) void k_tile(const Job<S>* __restri
 
         if (MODE == MODE_INIT) {
             // Procedure step 1: g = g^eq, f = f^eq at P = 0 with the given u.
-            const R ux = (R)J.in[3 * pitch + o], uy = (R)J.in[4 * pitch + o];
+            const R ux = (R)G(J.in)[3 * pitch + o], uy = (R)G(J.in)[4 * pitch + o];
             // g^eq of Sec. 3.1, term by term (keeps the small moving values exact)
             const R emu = c.eta * mu, ia = R(1) / c.a;
             const R jxa = ph * ux * ia, jya = ph * uy * ia;
@@ -762,9 +772,9 @@ __global__ __launch_bounds__(TileCfg<TY>::NT) void k_tile(const Job<S>* __restri
 #pragma unroll
             for (int i = 0; i < 9; ++i) dst[i] = o;
             int64_t mf = 0;
-            if (S::kFix) mf = llrint(J.in[o] * 0x1p40);
+            if (S::kFix) mf = llrint(G(J.in)[o] * 0x1p40);
             A::store(J.pop[0], pitch, dst, c, gg, ff, mf);
-            R* h0 = J.hist[0];
+            __attribute__((address_space(1))) R* h0 = G(J.hist[0]);
             h0[o] = ph; h0[pitch + o] = ux; h0[2 * pitch + o] = uy;
             h0[3 * pitch + o] = Sx; h0[4 * pitch + o] = Sy;
             continue;
@@ -786,9 +796,9 @@ __global__ __launch_bounds__(TileCfg<TY>::NT) void k_tile(const Job<S>* __restri
         R usolx = R(0), usoly = R(0), Fpx = R(0), Fpy = R(0);
         int own = -1;
         if (PART) {
-            own = J.owner[o];
+            own = G(J.owner)[o];
             if (own >= 0) {
-                const double* q = J.parts + own * PSTRIDE;
+                const __attribute__((address_space(1))) double* q = G(J.parts) + own * PSTRIDE;
                 // the domain's walls, not the tile's: a particle's support
                 // reaches tiles whose halo stays inside the domain
                 const int dw = WALL ? J.walls : 0;
@@ -825,9 +835,9 @@ __global__ __launch_bounds__(TileCfg<TY>::NT) void k_tile(const Job<S>* __restri
         }
         const R ax = z * (usolx - usx), ay = z * (usoly - usy);
         if (PART && own >= 0) {  // rho f dt and rho for the particle sums
-            J.pf[o] = rho * ax;
-            J.pf[pitch + o] = rho * ay;
-            J.pf[2 * pitch + o] = rho;
+            G(J.pf)[o] = rho * ax;
+            G(J.pf)[pitch + o] = rho * ay;
+            G(J.pf)[2 * pitch + o] = rho;
         }
         const R ux = first ? usx : usx + R(0.5) * ax;
         const R uy = first ? usy : usy + R(0.5) * ay;
@@ -852,15 +862,15 @@ __global__ __launch_bounds__(TileCfg<TY>::NT) void k_tile(const Job<S>* __restri
 
         if (MODE == MODE_OUT) {
             if (J.out) {
-                J.out[o] = (double)phx;
-                J.out[pitch + o] = (double)ux;
-                J.out[2 * pitch + o] = (double)uy;
-                J.out[3 * pitch + o] = (double)P;
+                G(J.out)[o] = (double)phx;
+                G(J.out)[pitch + o] = (double)ux;
+                G(J.out)[2 * pitch + o] = (double)uy;
+                G(J.out)[3 * pitch + o] = (double)P;
             }
             // energy densities (Eq. 2energy with psi; e_K = rho |u|^2 / 2)
             R qx, qy;
             {
-                const R* psi = st + pitch;
+                const auto* psi = st + pitch;
                 const R e_ = psi[rc + xe], w_ = psi[rc + xw], n_ = psi[rn + x], s_ = psi[rs + x];
                 const R ne = psi[rn + xe], nw = psi[rn + xw], se = psi[rs + xe], sw_ = psi[rs + xw];
                 qx = (e_ - w_) * R(1.0 / 3.0) + ((ne + se) - (nw + sw_)) * R(1.0 / 12.0);
@@ -962,7 +972,7 @@ __global__ __launch_bounds__(TileCfg<TY>::NT) void k_tile(const Job<S>* __restri
             A::store_bb(J.pop[par ^ 1], pitch, dst, o, bb, c, gk, fk, mk);
         else
             A::store(J.pop[par ^ 1], pitch, dst, c, gk, fk, mk);
-        R* hw = J.hist[par ^ 1];
+        __attribute__((address_space(1))) R* hw = G(J.hist[par ^ 1]);
         hw[o] = ph;
         hw[pitch + o] = ux;
         hw[2 * pitch + o] = uy;
@@ -987,12 +997,12 @@ __global__ __launch_bounds__(TileCfg<TY>::NT) void k_tile(const Job<S>* __restri
         if (tid < NPART) {
             double s = 0.0;
             for (int w = 0; w < NW; ++w) s += sred[w][tid];
-            J.part[(int64_t)(e - J.tile_base) * NPART + tid] = s;
+            G(J.part)[(int64_t)(e - J.tile_base) * NPART + tid] = s;
         }
         if (S::kFix && tid == NPART) {
             long long s = 0;
             for (int w = 0; w < NW; ++w) s += sired[w];
-            J.ipart[e - J.tile_base] = s;
+            G(J.ipart)[e - J.tile_base] = s;
         }
     }
 }
