@@ -613,13 +613,22 @@ __global__ __launch_bounds__(NT) void k3_node(Coef3 c, Planes3<T> P, int cur) {
 // of each new slice, from three slices of mu on the two-node ring (also in
 // LDS), with the sums k3_flux makes.  Every value the node update reads is
 // the one k3_node would read; only where it comes from differs.
+// Blocks are dealt to the 8 XCDs in turn; this renumbering gives each XCD a
+// contiguous range of the columns, so that the columns sharing ring rows run
+// on one XCD and meet in its L2.
+__device__ __forceinline__ int xcd_slab(int b, int G) {
+    const int q = G >> 3, r = G & 7;
+    const int k = b & 7, j = b >> 3;
+    return k * q + (k < r ? k : r) + j;
+}
+
 template <class T>
 __global__ __launch_bounds__(NT) void k3_march(Coef3 c, Planes3<T> P, int cur, int ntx, int nty) {
     __shared__ double s_phi[3][MP];
     __shared__ double s_S[3][3 * MP];
     __shared__ T s_u[3][3 * MP];
     __shared__ double s_mu[3][MP2];
-    int b = blockIdx.x;
+    int b = xcd_slab((int)blockIdx.x, (int)gridDim.x);
     const int tx = b % ntx;
     b /= ntx;
     const int ty = b % nty;
