@@ -251,21 +251,17 @@ __global__ __launch_bounds__(NT) void k3_phi(Coef3 c, Planes3<T> P, int cur) {
 
 // Eq. (potential): mu = (3 sigma/D) phi (phi^2 - 1) - (3 D sigma/8) lap phi
 // + (9 sigma/D) phi0^2 phi + (3 sigma/D) psi (3 phi^2 + phi0^2 - 1)
-// - (3 D sigma/8) lap psi
-template <class T>
-__global__ __launch_bounds__(NT) void k3_mu(Coef3 c, Planes3<T> P) {
-    const int64_t o = (int64_t)blockIdx.x * NT + threadIdx.x;
-    if (o >= c.n) return;
-    Nb nb;
-    neighbours(c, o, nb);
-    const double f = P.phi[o];
+// - (3 D sigma/8) lap psi, at one node from phi at x + c_i (phi_at(i); i = 0:
+// the node) and the node's statics phi0, psi, lap psi.
+template <class F>
+__device__ __forceinline__ double mu_of(const Coef3& c, F phi_at, double z, double q, double lq) {
+    const double f = phi_at(0);
     double lap = 0.0;
 #pragma unroll
-    for (int i = 1; i < Q; ++i) lap += wfd(i) * (P.phi[nb.o[i]] - f);
+    for (int i = 1; i < Q; ++i) lap += wfd(i) * (phi_at(i) - f);
     lap *= 6.0;
-    const double z = P.stat[o], q = P.stat[c.pitch + o], lq = P.stat[2 * c.pitch + o];
     const double a = 3.0 * c.sigma / c.Dw, b = 3.0 * c.Dw * c.sigma / 8.0;
-    P.mu[o] = a * f * (f - 1.0) * (f + 1.0) - b * lap + 3.0 * a * z * z * f + a * q * (3.0 * f * f + z * z - 1.0) - b * lq;
+    return a * f * (f - 1.0) * (f + 1.0) - b * lap + 3.0 * a * z * z * f + a * q * (3.0 * f * f + z * z - 1.0) - b * lq;
 }
 
 // Consistent mass flux S = M grad(mu) (rho1 - rho2)/2 at one node from mu at
@@ -622,6 +618,63 @@ __device__ __forceinline__ int xcd_slab(int b, int G) {
     return k * q + (k < r ? k : r) + j;
 }
 
+// In-slice offset of point p of a w-wide LDS slice holding a column at
+// (x0, y0) with its h-node ring, periodic; columns and rows past the ring a
+// ragged or narrow column needs are clamped into the grid and never read.
+__device__ __forceinline__ int ring_offset(const Coef3& c, int x0, int y0, int p, int w, int h) {
+    int gx = x0 + p % w - h, gy = y0 + p / w - h;
+    gx = gx < 0 ? gx + c.nx : (gx >= c.nx ? gx - c.nx : gx);
+    gy = gy < 0 ? gy + c.ny : (gy >= c.ny ? gy - c.ny : gy);
+    gx = gx < c.nx ? gx : c.nx - 1;
+    gy = gy < c.ny ? gy : c.ny - 1;
+    return gy * c.nx + gx;
+}
+
+// mu planes of the current level, marching along z over the columns of
+// k3_march with three slices of phi and their one-node ring in LDS.
+template <class T>
+__global__ __launch_bounds__(NT) void k3_mu(Coef3 c, Planes3<T> P, int ntx, int nty) {
+    __shared__ double s_phi[3][MP];
+    int b = xcd_slab((int)blockIdx.x, (int)gridDim.x);
+    const int tx = b % ntx;
+    b /= ntx;
+    const int ty = b % nty;
+    const int z0 = (b / nty) * MZ;
+    const int z1 = z0 + MZ < c.nz ? z0 + MZ : c.nz;
+    const int x0 = tx * MX, y0 = ty * MY;
+    const int t = threadIdx.x;
+    const int x = x0 + (t % MX), y = y0 + t / MX;
+    const bool in = x < c.nx && y < c.ny;
+    int off[2];
+#pragma unroll
+    for (int r = 0; r < 2; ++r) off[r] = ring_offset(c, x0, y0, t + r * NT < MP ? t + r * NT : MP - 1, MW, 1);
+    auto load = [&](int s) {  // phi of slice s into slot (s - z0 + 1) % 3
+        const int slot = (s - z0 + 1) % 3;
+        const int zz = s < 0 ? s + c.nz : (s >= c.nz ? s - c.nz : s);
+        const int64_t base = (int64_t)zz * c.nx * c.ny;
+#pragma unroll
+        for (int r = 0; r < 2; ++r) {
+            const int p = t + r * NT;
+            if (p < MP) s_phi[slot][p] = P.phi[base + off[r]];
+        }
+    };
+    load(z0 - 1);
+    load(z0);
+    const int q = (t / MX + 1) * MW + (t % MX) + 1;
+    for (int k = 0; z0 + k < z1; ++k) {
+        const int z = z0 + k;
+        __syncthreads();  // the slot written next is no longer read
+        load(z + 1);
+        __syncthreads();
+        if (in) {
+            const int64_t o = ((int64_t)z * c.ny + y) * c.nx + x, pt = c.pitch;
+            const double* sl[3] = {s_phi[k % 3], s_phi[(k + 1) % 3], s_phi[(k + 2) % 3]};
+            P.mu[o] = mu_of(c, [&](int i) { return sl[czv(i) + 1][q + cyv(i) * MW + cxv(i)]; }, P.stat[o],
+                            P.stat[pt + o], P.stat[2 * pt + o]);
+        }
+    }
+}
+
 template <class T>
 __global__ __launch_bounds__(NT) void k3_march(Coef3 c, Planes3<T> P, int cur, int ntx, int nty) {
     __shared__ double s_phi[3][MP];
@@ -644,14 +697,7 @@ __global__ __launch_bounds__(NT) void k3_march(Coef3 c, Planes3<T> P, int cur, i
     // ring (two rounds) and the two-node ring (three rounds); columns and rows
     // past the ring a ragged or narrow tile needs are clamped into the grid
     // and never read
-    auto ring_off = [&](int p, int w, int h) {
-        int gx = x0 + p % w - h, gy = y0 + p / w - h;
-        gx = gx < 0 ? gx + c.nx : (gx >= c.nx ? gx - c.nx : gx);
-        gy = gy < 0 ? gy + c.ny : (gy >= c.ny ? gy - c.ny : gy);
-        gx = gx < c.nx ? gx : c.nx - 1;
-        gy = gy < c.ny ? gy : c.ny - 1;
-        return gy * c.nx + gx;
-    };
+    auto ring_off = [&](int p, int w, int h) { return ring_offset(c, x0, y0, p, w, h); };
     int off[2], off2[3];
 #pragma unroll
     for (int r = 0; r < 2; ++r) off[r] = ring_off(t + r * NT < MP ? t + r * NT : MP - 1, MW, 1);
@@ -905,14 +951,22 @@ Planes3<T> planes(lbm3_domain* d) {
     return P;
 }
 
+// the marching kernels' grid: MX x MY columns of MZ slices
+struct March {
+    int ntx, nty, nzc;
+    dim3 grid() const { return dim3((unsigned)((int64_t)ntx * nty * nzc)); }
+};
+March march(const Coef3& c) { return March{(c.nx + MX - 1) / MX, (c.ny + MY - 1) / MY, (c.nz + MZ - 1) / MZ}; }
+
 // phi of the current level from the populations, then mu, and S unless the
 // marching node update forms it
 template <class T>
 int fields3(lbm3_domain* d, bool with_S) {
     Planes3<T> P = planes<T>(d);
     const dim3 g((unsigned)d->blocks), b(NT);
+    const March m = march(d->c);
     hipLaunchKernelGGL(k3_phi<T>, g, b, 0, d->stream, d->c, P, d->cur);
-    hipLaunchKernelGGL(k3_mu<T>, g, b, 0, d->stream, d->c, P);
+    hipLaunchKernelGGL(k3_mu<T>, m.grid(), b, 0, d->stream, d->c, P, m.ntx, m.nty);
     if (with_S) hipLaunchKernelGGL(k3_flux<T>, g, b, 0, d->stream, d->c, P);
     HIPCHK3(hipGetLastError());
     return LBM_OK;
@@ -925,9 +979,8 @@ int step3(lbm3_domain* d, int64_t nsteps) {
         int rc = fields3<T>(d, false);
         if (rc) return rc;
         Planes3<T> P = planes<T>(d);
-        const int ntx = (d->c.nx + MX - 1) / MX, nty = (d->c.ny + MY - 1) / MY, nzc = (d->c.nz + MZ - 1) / MZ;
-        hipLaunchKernelGGL(k3_march<T>, dim3((unsigned)((int64_t)ntx * nty * nzc)), dim3(NT), 0, d->stream, d->c, P,
-                           d->cur, ntx, nty);
+        const March m = march(d->c);
+        hipLaunchKernelGGL(k3_march<T>, m.grid(), dim3(NT), 0, d->stream, d->c, P, d->cur, m.ntx, m.nty);
         HIPCHK3(hipGetLastError());
         d->cur ^= 1;
         d->c.first = 0;
@@ -972,7 +1025,8 @@ int create3(lbm3_domain* d, const double* phi, const double* phi0, const double*
     HIPCHK3(hipMemcpyAsync(P.phi, phi, n * 8, hipMemcpyHostToDevice, d->stream));
     hipLaunchKernelGGL(k3_static, g, b, 0, d->stream, d->c, (const double*)st, P.stat);
     hipLaunchKernelGGL(k3_lap_psi, g, b, 0, d->stream, d->c, P.stat);
-    hipLaunchKernelGGL(k3_mu<T>, g, b, 0, d->stream, d->c, P);
+    const March m = march(d->c);
+    hipLaunchKernelGGL(k3_mu<T>, m.grid(), b, 0, d->stream, d->c, P, m.ntx, m.nty);
     hipLaunchKernelGGL(k3_flux<T>, g, b, 0, d->stream, d->c, P);
     hipLaunchKernelGGL(k3_equilibrium<T>, g, b, 0, d->stream, d->c, P, (const double*)(st + 2 * pt));
     HIPCHK3(hipGetLastError());
