@@ -8,12 +8,12 @@
 // tensor built from S).  In 3-D a 64 x 4 x 4 block would have to rebuild the
 // order parameter from 15 populations at ~7x as many ring nodes as it owns.
 // Instead the order parameter and mu are written once per step as FP64
-// planes (8 + 8 bytes per node; mu reads its one-node ring of phi through the
-// caches), and the node update (k3_march) marches along z over a 64 x 4
-// column, holding slices of phi and the lagged velocity on the one-node ring
-// and of mu on the two-node ring in LDS, forming S on the ring there, so
-// that each of those values is read from memory under twice per step instead
-// of once per neighbour that needs it.
+// planes (8 + 8 bytes per node).  The mu kernel and the node update
+// (k3_march) march along z over 64 x 4 columns, holding slices of what they
+// read on rings in LDS (mu: phi on the one-node ring; the node update: phi
+// and the lagged velocity on the one-node ring and mu on the two-node ring,
+// forming S on the ring there), so that each of those values is loaded under
+// twice per step instead of once per neighbour that needs it.
 //
 // Arithmetic is FP64 for either storage; FP32 storage rounds what is stored.
 //
