@@ -247,3 +247,20 @@ def test_cap_fit_recovers_a_known_angle(theta):
     y, x = np.mgrid[0:ny, 0:nx].astype(float)
     phi = np.tanh((Rc - np.hypot(x - nx / 2, y - yc)) / (D / 2))
     assert abs(cap_angle(phi, ys) - theta) < 0.2
+
+
+@pytest.mark.parametrize("theta", [45.0, 90.0, 135.0])
+def test_sphere_cap_fit_recovers_a_known_angle(theta):
+    """The three-dimensional measurement: on a drawn diffuse spherical cap
+    that meets the wall plane z = zs at a known angle (off the grid's
+    symmetry: centre at a fractional position), the sphere fit through the
+    phi = 0 crossings returns that angle within 0.2 degrees."""
+    from capfit import cap_angle_3d
+    nx, ny, nz, zs, D = 96, 96, 64, 11.5, 4.0
+    t = math.radians(theta)
+    Rc = 18.0
+    zc = zs - Rc * math.cos(t)
+    z, y, x = np.mgrid[0:nz, 0:ny, 0:nx].astype(float)
+    phi = np.tanh((Rc - np.sqrt((x - 47.3) ** 2 + (y - 48.6) ** 2 + (z - zc) ** 2)) / (D / 2))
+    assert abs(cap_angle_3d(phi, zs) - theta) < 0.2
+
