@@ -142,3 +142,23 @@ def test_3d_workspace_size_and_validation_host_only():
                 dict(rho2=0.0), dict(solid_eps=0.0)):
         assert nbytes(**bad) == 0, bad
         assert L.lbm3_last_error().decode()
+
+
+def test_grid_size_limits_host_only():
+    """Node indices are 32-bit: the largest grids below 2^31 nodes are sized,
+    the first above it is refused (2-D step and smoothing; 3-D)."""
+    lbmgls = _lib()
+    from paper_2311_05097_amd import workloads as W
+    L = lbmgls.lib()
+    p = W.config1().params
+    assert lbmgls.workspace_bytes(dict(p, nx=46340, ny=46340), "fp32") > 2 * 18 * 4 * 46340 ** 2
+    with pytest.raises(lbmgls.LbmError):
+        lbmgls.workspace_bytes(dict(p, nx=46341, ny=46341), "fp32")
+    assert L.lbm_smooth_workspace_bytes(46340, 46340) > 0
+    assert L.lbm_smooth_workspace_bytes(46341, 46341) == 0
+
+    def nbytes3(n):
+        return L.lbm3_workspace_bytes(ctypes.byref(lbmgls.make_params3(dict(nx=n, ny=n, nz=n), "fp32")))
+
+    assert nbytes3(1290) > 2 * 30 * 4 * 1290 ** 3
+    assert nbytes3(1291) == 0 and b"2^31" in L.lbm3_last_error()
