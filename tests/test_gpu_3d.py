@@ -220,3 +220,15 @@ def test_laplace_law_sphere_gpu(gpu, R, n):
     d.close()
     assert abs(ratio - 1) < 0.05
     assert umax < 2e-5
+
+
+def test_zero_steps_change_nothing_and_negative_steps_are_refused(gpu):
+    w = _small()
+    d = gpu.Domain3(w.params, *w.arrays(), storage="fp32")
+    d.step(2)
+    before = d.read()
+    d.step(0)
+    with pytest.raises(gpu.LbmError):
+        d.step(-1)
+    for a, b in zip(before, d.read()):
+        assert np.array_equal(a, b)

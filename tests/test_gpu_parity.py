@@ -278,3 +278,16 @@ def test_config2_shape_1000_steps(gpu, c2_small, storage):
     print(f"\nC2 shape 128^2 {storage} 1000 steps (2-norm/max-norm): {fmt(errs)} mass_drift={drift:.2e}")
     assert all(np.all(np.isfinite(x)) for x in ref)
     check(errs, BAR[storage])
+
+
+def test_zero_steps_change_nothing_and_negative_steps_are_refused(gpu):
+    w = W.random_state(40, 24, seed=3, rho2=0.3, mu2=0.04)
+    d = gpu.Domain(w.params, *w.arrays(), storage="fp32")
+    d.step(3)
+    before = d.read()
+    d.step(0)
+    assert d.steps == 3
+    with pytest.raises(gpu.LbmError):
+        d.step(-1)
+    for a, b in zip(before, d.read()):
+        assert np.array_equal(a, b)
