@@ -57,6 +57,8 @@ def n_static(w) -> int:
     import numpy as np
     ct = np.asarray(w.cos_theta)
     return 2 if (w.particles is not None and len(w.particles)) or np.ptp(ct) > 0 else 1
+
+
 DTYPE = {"fp64": "f64", "fp32": "f32", "fp16dev": "f32 (fp16 storage)", "bf16dev": "f32 (bf16 storage)"}
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
 # relative 2-norm error of a served job's final order parameter against the
@@ -69,6 +71,17 @@ def kernel_source_hash() -> str:
     for f in ("paper_2311_05097_amd/csrc/lbm_device.h", "paper_2311_05097_amd/csrc/lbm_abi.hip"):
         h.update(open(os.path.join(ROOT, f), "rb").read())
     return h.hexdigest()[:16]
+
+
+def segment_sizes(steps: int, warmup: int, horizon: int):
+    """Lengths of the timed segments of a case that stays finite only up to
+    step `horizon`: each starts from the state after `warmup` steps, so each
+    is at most horizon - warmup steps long; together they make `steps`."""
+    if warmup >= horizon:
+        raise SystemExit(f"bench.py: this case leaves the finite range soon after step {horizon}; "
+                         f"the warmup ({warmup}) must stay below it")
+    per = min(steps, horizon - warmup)
+    return [min(per, steps - k) for k in range(0, steps, per)]
 
 
 def run_gpu(workload, storage: str, steps: int, warmup: int, tile: int = 0, samples: int = 5,
@@ -97,23 +110,18 @@ def run_gpu(workload, storage: str, steps: int, warmup: int, tile: int = 0, samp
     torch.cuda.synchronize()
     kms = []
     if horizon:
-        if warmup >= horizon:
-            raise SystemExit(f"bench.py: {workload.name} leaves the finite range soon after step {horizon}; "
-                             f"the warmup ({warmup}) must stay below it")
         saved = d.export_state()
-        per = min(steps, horizon - warmup)
-        nseg = -(-steps // per)
-        dt, finite, done = 0.0, True, 0
-        for k in range(nseg):
+        sizes = segment_sizes(steps, warmup, horizon)
+        per, nseg = sizes[0], len(sizes)
+        dt, finite = 0.0, True
+        for k, n in enumerate(sizes):
             if k:
                 d.import_state(saved)
-            n = min(per, steps - done)
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             d.step(n)
             torch.cuda.synchronize()
             dt += time.perf_counter() - t0
-            done += n
             kms.append(d.last_step_ms)
             finite = finite and all(np.isfinite(a).all() for a in d.read())
         segments = dict(segment_steps=per, segments=nseg, restart_step=warmup)
