@@ -64,7 +64,9 @@ enum {
 enum { LBM_TILE_AUTO = 0, LBM_TILE_64x4 = 4, LBM_TILE_64x8 = 8, LBM_TILE_64x16 = 16, LBM_TILE_64x32 = 32 };
 
 typedef struct {
-    int32_t nx, ny;        /* lattice size (periodic unless walled); nx, ny >= 8  */
+    int32_t nx, ny;        /* lattice size (periodic unless walled); nx, ny >= 8;
+                              nx * ny < 2^31, and <= 2^30 for FP32 and 16-bit
+                              storage (planes addressed by 32-bit byte offsets) */
     int32_t storage;       /* LBM_STORE_*                                          */
     int32_t tile;          /* LBM_TILE_*                                           */
     double d0;             /* c_s^2 / c^2 in (0, 1); D2Q9 weights (Sec. 4)         */

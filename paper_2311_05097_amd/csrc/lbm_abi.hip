@@ -85,6 +85,11 @@ int validate(const lbm_params* p) {
     if ((int64_t)p->nx * p->ny >= (int64_t)1 << 31) return fail(LBM_EINVAL, "domain too large (2^31 nodes)");
     if (p->storage < LBM_STORE_FP64 || p->storage > LBM_STORE_BF16DEV)
         return fail(LBM_EUNSUPPORTED, "unknown storage mode");
+    // FP32 and 16-bit planes are addressed by 32-bit byte offsets (4 GiB a
+    // plane): at most 2^30 nodes, about the most their state fits on one
+    // device anyway
+    if (p->storage != LBM_STORE_FP64 && ((int64_t)p->nx * p->ny + 63) / 64 * 64 > (int64_t)1 << 30)
+        return fail(LBM_EINVAL, "domain too large for FP32 or 16-bit storage (2^30 nodes)");
     if (!(p->tile == LBM_TILE_AUTO || p->tile == LBM_TILE_64x4 || p->tile == LBM_TILE_64x8 ||
           p->tile == LBM_TILE_64x16 || p->tile == LBM_TILE_64x32))
         return fail(LBM_EUNSUPPORTED, "unknown tile shape");

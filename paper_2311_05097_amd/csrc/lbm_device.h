@@ -333,19 +333,47 @@ __device__ __forceinline__ __attribute__((address_space(1))) T* G(T* p) {
 
 template <class S> struct Access;
 
+// Element o of a plane.  A plane of 2- or 4-byte elements is addressed by a
+// 32-bit byte offset from its base, which is the same for the whole block:
+// each load or store then takes the base in scalar registers and one 32-bit
+// vector offset, with no 64-bit address arithmetic per access (such planes
+// hold at most 4 GiB: FP32 and 16-bit storage take at most 2^30 nodes, more
+// than fit in the device's memory).  FP64 planes keep 64-bit indexing
+// (offsets measured no faster there).
+template <class T>
+__device__ __forceinline__ T* boff(T* base, uint32_t off) {
+    using B = __attribute__((address_space(1))) char;
+    return (T*)((B*)base + off);
+}
+template <class R>
+__device__ __forceinline__ __attribute__((address_space(1))) R& pel(R* plane, uint32_t o) {
+    if constexpr (sizeof(R) == 8)
+        return G(plane)[o];
+    else
+        return *boff(G(plane), o * (uint32_t)sizeof(R));
+}
+template <class R>
+__device__ __forceinline__ const __attribute__((address_space(1))) R& pel(
+    const __attribute__((address_space(1))) R* plane, uint32_t o) {
+    if constexpr (sizeof(R) == 8)
+        return plane[o];
+    else
+        return *boff(plane, o * (uint32_t)sizeof(R));
+}
+
 template <class Sf>
 struct AccessFull {  // FP64 / FP32: plain values
     using R = typename Sf::R;
     using Pop = typename Sf::Pop;
     static __device__ __forceinline__ R phi(const Pop& P, int64_t pitch, uint32_t o, const Coef<R>&) {
-        const __attribute__((address_space(1))) R* p = G(P.p);
-        return ((p[o] + (p[pitch + o] + p[3 * pitch + o])) + (p[2 * pitch + o] + p[4 * pitch + o]))
-             + ((p[5 * pitch + o] + p[7 * pitch + o]) + (p[6 * pitch + o] + p[8 * pitch + o]));
+        R* p = P.p;
+        return ((pel(p, o) + (pel(p + pitch, o) + pel(p + 3 * pitch, o))) + (pel(p + 2 * pitch, o) + pel(p + 4 * pitch, o)))
+             + ((pel(p + 5 * pitch, o) + pel(p + 7 * pitch, o)) + (pel(p + 6 * pitch, o) + pel(p + 8 * pitch, o)));
     }
     static __device__ __forceinline__ void load_g(const Pop& P, int64_t pitch, uint32_t o, const Coef<R>&,
                                                   R* g, int64_t& mfix) {
 #pragma unroll
-        for (int i = 0; i < 9; ++i) g[i] = G(P.p)[i * pitch + o];
+        for (int i = 0; i < 9; ++i) g[i] = pel(P.p + i * pitch, o);
         mfix = 0;
     }
     static __device__ __forceinline__ R phi_of(const R* g, int64_t, const Coef<R>&) {
@@ -354,14 +382,14 @@ struct AccessFull {  // FP64 / FP32: plain values
     static __device__ __forceinline__ void load_f(const Pop& P, int64_t pitch, uint32_t o, const Coef<R>&,
                                                   R* f) {
 #pragma unroll
-        for (int i = 0; i < 9; ++i) f[i] = G(P.p)[(9 + i) * pitch + o];
+        for (int i = 0; i < 9; ++i) f[i] = pel(P.p + (9 + i) * pitch, o);
     }
     static __device__ __forceinline__ void store(const Pop& P, int64_t pitch, const uint32_t* dst,
                                                  const Coef<R>&, const R* g, const R* f, int64_t) {
 #pragma unroll
-        for (int i = 0; i < 9; ++i) G(P.p)[i * pitch + dst[i]] = g[i];
+        for (int i = 0; i < 9; ++i) pel(P.p + i * pitch, dst[i]) = g[i];
 #pragma unroll
-        for (int i = 0; i < 9; ++i) G(P.p)[(9 + i) * pitch + dst[i]] = f[i];
+        for (int i = 0; i < 9; ++i) pel(P.p + (9 + i) * pitch, dst[i]) = f[i];
     }
     // next to walls: the crossing directions go to the opposite planes at o
     static __device__ __forceinline__ void store_bb(const Pop& P, int64_t pitch, const uint32_t* dst,
@@ -372,8 +400,8 @@ struct AccessFull {  // FP64 / FP32: plain values
             const bool cr = crosses(i, bb);
             const int64_t pl = cr ? opposite(i) : i;
             const uint32_t d = cr ? o : dst[i];
-            G(P.p)[pl * pitch + d] = g[i];
-            G(P.p)[(9 + pl) * pitch + d] = f[i];
+            pel(P.p + pl * pitch, d) = g[i];
+            pel(P.p + (9 + pl) * pitch, d) = f[i];
         }
     }
 };
@@ -401,7 +429,7 @@ struct AccessHalf {  // 16-bit codes + fixed-point rest population
     static __device__ __forceinline__ float phi(const Pop& P, int64_t pitch, uint32_t o, const Coef<float>& c) {
         double s = 0.0;
 #pragma unroll
-        for (int i = 0; i < 8; ++i) s += gfix(c, G(P.gm)[i * pitch + o]);
+        for (int i = 0; i < 8; ++i) s += gfix(c, pel(P.gm + i * pitch, o));
         return fix2f(G(P.g0)[o] + (int64_t)s);
     }
     static __device__ __forceinline__ void load_g(const Pop& P, int64_t pitch, uint32_t o, const Coef<float>& c,
@@ -410,7 +438,7 @@ struct AccessHalf {  // 16-bit codes + fixed-point rest population
         double s = 0.0;
 #pragma unroll
         for (int i = 0; i < 8; ++i) {
-            const uint16_t code = G(P.gm)[i * pitch + o];
+            const uint16_t code = pel(P.gm + i * pitch, o);
             g[i + 1] = Sh::dec(code) * c.isg;
             s += gfix(c, code);
         }
@@ -423,7 +451,7 @@ struct AccessHalf {  // 16-bit codes + fixed-point rest population
     static __device__ __forceinline__ void load_f(const Pop& P, int64_t pitch, uint32_t o, const Coef<float>& c,
                                                   float* f) {
 #pragma unroll
-        for (int i = 0; i < 9; ++i) f[i] = Sh::dec(G(P.fm)[i * pitch + o]) * c.isf;
+        for (int i = 0; i < 9; ++i) f[i] = Sh::dec(pel(P.fm + i * pitch, o)) * c.isf;
     }
     // mfix: the node's conserved sum_i g_i in fixed point; g_0 is written so
     // that the stored values sum to it exactly.
@@ -434,12 +462,12 @@ struct AccessHalf {  // 16-bit codes + fixed-point rest population
 #pragma unroll
         for (int i = 0; i < 8; ++i) {
             const uint16_t code = Sh::enc(g[i + 1] * c.sg);
-            G(P.gm)[i * pitch + dst[i + 1]] = code;
+            pel(P.gm + i * pitch, dst[i + 1]) = code;
             s += gfix(c, code);
         }
         G(P.g0)[dst[0]] = mfix - (int64_t)s;
 #pragma unroll
-        for (int i = 0; i < 9; ++i) G(P.fm)[i * pitch + dst[i]] = Sh::enc(f[i] * c.sf);
+        for (int i = 0; i < 9; ++i) pel(P.fm + i * pitch, dst[i]) = Sh::enc(f[i] * c.sf);
     }
     // next to walls: the crossing directions go to the opposite planes at o
     // (dst[0] == o); the stored values still sum to mfix at this node's share
@@ -452,7 +480,7 @@ struct AccessHalf {  // 16-bit codes + fixed-point rest population
             const bool cr = crosses(i + 1, bb);
             const int64_t pl = cr ? opposite(i + 1) : i + 1;
             const uint16_t code = Sh::enc(g[i + 1] * c.sg);
-            G(P.gm)[(pl - 1) * pitch + (cr ? o : dst[i + 1])] = code;
+            pel(P.gm + (pl - 1) * pitch, cr ? o : dst[i + 1]) = code;
             s += gfix(c, code);
         }
         G(P.g0)[dst[0]] = mfix - (int64_t)s;
@@ -460,7 +488,7 @@ struct AccessHalf {  // 16-bit codes + fixed-point rest population
         for (int i = 0; i < 9; ++i) {
             const bool cr = crosses(i, bb);
             const int64_t pl = cr ? opposite(i) : i;
-            G(P.fm)[pl * pitch + (cr ? o : dst[i])] = Sh::enc(f[i] * c.sf);
+            pel(P.fm + pl * pitch, cr ? o : dst[i]) = Sh::enc(f[i] * c.sf);
         }
     }
 };
@@ -578,12 +606,12 @@ __global__ __launch_bounds__(TileCfg<TY>::NT) void k_tile(const Job<S>* __restri
             A::load_g(cur, pitch, o, c, g[kk], mfix[kk]);
             A::load_f(cur, pitch, o, c, f[kk]);
 #pragma unroll
-            for (int v = 0; v < 5; ++v) hp[kk][v] = hprev[v * pitch + o];
+            for (int v = 0; v < 5; ++v) hp[kk][v] = pel(hprev + v * pitch, o);
             *sp = S::kRel ? (RX)hp[kk][0] + (RX)A::phi_of(g[kk], mfix[kk], c) : (RX)A::phi_of(g[kk], mfix[kk], c);
         } else {
-            *sp = S::kRel ? (RX)hprev[o] + (RX)A::phi(cur, pitch, o, c) : (RX)A::phi(cur, pitch, o, c);
+            *sp = S::kRel ? (RX)pel(hprev, o) + (RX)A::phi(cur, pitch, o, c) : (RX)A::phi(cur, pitch, o, c);
         }
-        zz[k] = st[o];
+        zz[k] = pel(st, o);
     }
     for (int p = tid; p < NRING; p += NTH) {
         int ly, lx;
@@ -601,7 +629,7 @@ __global__ __launch_bounds__(TileCfg<TY>::NT) void k_tile(const Job<S>* __restri
         if (MODE == MODE_INIT)
             sphi[ly * W3 + lx] = (RX)G(J.in)[o];
         else if (S::kRel)
-            sphi[ly * W3 + lx] = (RX)hprev[o] + (RX)A::phi(cur, pitch, o, c);
+            sphi[ly * W3 + lx] = (RX)pel(hprev, o) + (RX)A::phi(cur, pitch, o, c);
         else
             sphi[ly * W3 + lx] = A::phi(cur, pitch, o, c);
     }
@@ -614,9 +642,9 @@ __global__ __launch_bounds__(TileCfg<TY>::NT) void k_tile(const Job<S>* __restri
         if (p < H2 * W2) {
             const int ly = p / W2, lx = p - ly * W2;
             const uint32_t o = (uint32_t)(s_row[ly + 1] + s_col[lx + 1]);
-            bz[k] = st[o];
-            bpsi[k] = st[pitch + o];
-            blp[k] = st[2 * pitch + o];
+            bz[k] = pel(st, o);
+            bpsi[k] = pel(st + pitch, o);
+            blp[k] = pel(st + 2 * pitch, o);
         }
     }
 #pragma unroll
@@ -632,8 +660,8 @@ __global__ __launch_bounds__(TileCfg<TY>::NT) void k_tile(const Job<S>* __restri
             const int yy = y0 + ly - 1, xx = x0 + lx - 1;
             const bool gy = (walls & 1) && (yy < 0 || yy >= ny), gx = (walls & 2) && (xx < 0 || xx >= nx);
             const R sg = gx != gy ? R(-1) : R(1);
-            cux[k] = sg * hprev[pitch + o];
-            cuy[k] = sg * hprev[2 * pitch + o];
+            cux[k] = sg * pel(hprev + pitch, o);
+            cuy[k] = sg * pel(hprev + 2 * pitch, o);
         }
     }
     __syncthreads();
@@ -678,7 +706,7 @@ __global__ __launch_bounds__(TileCfg<TY>::NT) void k_tile(const Job<S>* __restri
         A::load_g(cur, pitch, own[0], c, gn, mn);
         A::load_f(cur, pitch, own[0], c, fn);
 #pragma unroll
-        for (int v = 0; v < 5; ++v) hn[v] = hprev[v * pitch + own[0]];
+        for (int v = 0; v < 5; ++v) hn[v] = pel(hprev + v * pitch, own[0]);
     }
 #pragma unroll
     for (int k = 0; k < NOWN; ++k) {
@@ -703,7 +731,7 @@ __global__ __launch_bounds__(TileCfg<TY>::NT) void k_tile(const Job<S>* __restri
                     A::load_g(cur, pitch, o1, c, gn, mn);
                     A::load_f(cur, pitch, o1, c, fn);
 #pragma unroll
-                    for (int v = 0; v < 5; ++v) hn[v] = hprev[v * pitch + o1];
+                    for (int v = 0; v < 5; ++v) hn[v] = pel(hprev + v * pitch, o1);
                 }
             }
         }
@@ -972,12 +1000,12 @@ __global__ __launch_bounds__(TileCfg<TY>::NT) void k_tile(const Job<S>* __restri
             A::store_bb(J.pop[par ^ 1], pitch, dst, o, bb, c, gk, fk, mk);
         else
             A::store(J.pop[par ^ 1], pitch, dst, c, gk, fk, mk);
-        __attribute__((address_space(1))) R* hw = G(J.hist[par ^ 1]);
-        hw[o] = ph;
-        hw[pitch + o] = ux;
-        hw[2 * pitch + o] = uy;
-        hw[3 * pitch + o] = Sx;
-        hw[4 * pitch + o] = Sy;
+        R* hw = J.hist[par ^ 1];
+        pel(hw, o) = ph;
+        pel(hw + pitch, o) = ux;
+        pel(hw + 2 * pitch, o) = uy;
+        pel(hw + 3 * pitch, o) = Sx;
+        pel(hw + 4 * pitch, o) = Sy;
     }
 
     if (MODE == MODE_OUT) {

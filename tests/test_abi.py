@@ -146,14 +146,21 @@ def test_3d_workspace_size_and_validation_host_only():
 
 def test_grid_size_limits_host_only():
     """Node indices are 32-bit: the largest grids below 2^31 nodes are sized,
-    the first above it is refused (2-D step and smoothing; 3-D)."""
+    the first above it is refused (2-D FP64 step and smoothing; 3-D); FP32 and
+    16-bit planes are addressed by 32-bit byte offsets, which holds them to
+    2^30 nodes."""
     lbmgls = _lib()
     from paper_2311_05097_amd import workloads as W
     L = lbmgls.lib()
     p = W.config1().params
-    assert lbmgls.workspace_bytes(dict(p, nx=46340, ny=46340), "fp32") > 2 * 18 * 4 * 46340 ** 2
+    assert lbmgls.workspace_bytes(dict(p, nx=46340, ny=46340), "fp64") > 2 * 18 * 8 * 46340 ** 2
     with pytest.raises(lbmgls.LbmError):
-        lbmgls.workspace_bytes(dict(p, nx=46341, ny=46341), "fp32")
+        lbmgls.workspace_bytes(dict(p, nx=46341, ny=46341), "fp64")
+    for st in ("fp32", "fp16dev", "bf16dev"):
+        assert lbmgls.workspace_bytes(dict(p, nx=32768, ny=32768), st) > 2 * 17 * 2 * 32768 ** 2
+        for nx, ny in ((32769, 32768), (46340, 46340)):
+            with pytest.raises(lbmgls.LbmError, match="2\\^30"):
+                lbmgls.workspace_bytes(dict(p, nx=nx, ny=ny), st)
     assert L.lbm_smooth_workspace_bytes(46340, 46340) > 0
     assert L.lbm_smooth_workspace_bytes(46341, 46341) == 0
 
